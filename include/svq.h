@@ -1,0 +1,198 @@
+/*
+ * svq -- single-GPU state-vector simulation under lazy qubit reordering.
+ *
+ * C ABI of libsvq.so.  Plain pointers and sizes only; every call returns an
+ * svq_status and never throws.  Device pointers are HIP device memory on the
+ * current device; "stream" is a hipStream_t passed as void* (NULL = the
+ * default stream).
+ *
+ * Terms from "Lazy Qubit Reordering for Accelerating Parallel
+ * State-Vector-based Quantum Circuit Simulation":
+ *   - the state vector holds 2^n complex amplitudes, qubit q = bit q of the
+ *     logical index, qubit 0 the least significant bit (Section
+ *     "Preliminaries", eq. sv);
+ *   - the buffer is split into 2^g chunks by its g most significant physical
+ *     bits; those bits hold the "global" qubits Q_G, the others the local
+ *     qubits Q_L (Section "State vector distribution", eq. sub_sv;
+ *     Section "Qubit mapping", eq. qubit_division).  On one GPU the chunks
+ *     stand in for the paper's processing elements;
+ *   - a qubit reordering (QR) exchanges equal-size subsets of Q_L and Q_G,
+ *     swapping the elements whose indices differ in the exchanged bit pairs
+ *     (Section "Qubit reordering"); here it is an in-HBM bit permutation;
+ *   - a gate (QSU, eq. update_sv_reorder) or Pauli string (EVC, eq. evc) is
+ *     only ever applied to data inside one chunk (narrow access, constraint
+ *     C2, eq. qr_map_cond).
+ *
+ * Physical layout: the handle keeps pos[q], the physical bit that holds
+ * logical qubit q.  Calls that reorder qubits change pos[] but never the
+ * logical state; sv_get_amplitudes always returns logical order.
+ */
+#ifndef SVQ_C_ABI_H
+#define SVQ_C_ABI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct svq_state_s *svq_state;
+
+typedef enum { SVQ_C64 = 0, SVQ_C128 = 1 } svq_dtype;
+
+/* EAGER: breadth-first order, reorder as soon as an operator is wide (the ad
+ * hoc baseline of the paper's evaluation).  LAZY: time-space tiling, Algs.
+ * 1-3 for circuits and Alg. 6 with diagonalization for Pauli sums. */
+typedef enum { SVQ_EAGER = 0, SVQ_LAZY = 1 } svq_sched;
+
+typedef enum {
+    SVQ_OK = 0,
+    SVQ_EINVAL = -1,     /* bad argument; the handle is unchanged */
+    SVQ_ENOMEM = -2,     /* device or host allocation failed */
+    SVQ_EHIP = -3,       /* a HIP call failed; the handle is poisoned */
+    SVQ_ESHAPE = -4,     /* sizes inconsistent (buffer too small, n out of range) */
+    SVQ_EUNSUP = -5,     /* valid but not supported by this build */
+    SVQ_EPOISONED = -6   /* an earlier HIP failure poisoned the handle */
+} svq_status;
+
+typedef enum {
+    SVQ_H = 0, SVQ_X = 1, SVQ_Y = 2, SVQ_Z = 3, SVQ_S = 4, SVQ_T = 5,
+    SVQ_RX = 6, SVQ_RY = 7, SVQ_RZ = 8,
+    SVQ_CNOT = 9,      /* q[0] control, q[1] target */
+    SVQ_CZ = 10,
+    SVQ_CPHASE = 11,   /* diag(1,1,1,e^{i t}) */
+    SVQ_GIVENS = 12,   /* rotation by t/2 in span{|q0=1,q1=0>, |q0=0,q1=1>} */
+    SVQ_SWAP = 13,
+    SVQ_U1 = 14,       /* dense 2x2 from mat[] */
+    SVQ_U2 = 15        /* dense 4x4 from mat[] */
+} svq_gate_kind;
+
+/* One gate.  The gate's matrix uses local index l = sum_j bit_{q[j]} 2^j, so
+ * q[0] is the low bit (the paper leaves the order open).  The angle is
+ * theta[param] when param >= 0, else `angle`.  Parametric kinds follow
+ * U(t) = exp(-i t K): RX/RY/RZ K = sigma/2; CPHASE K = -|11><11|;
+ * GIVENS K = (X_q0 Y_q1 - Y_q0 X_q1)/4. */
+typedef struct {
+    int32_t kind;
+    int32_t q[2];
+    int32_t param;
+    double angle;
+    double mat[32];    /* U1: 2x2, U2: 4x4, row-major complex as (re, im) */
+} svq_gate;
+
+/* Pauli string (eq. pauli_form): X at q if only x has bit q, Z if only z,
+ * Y if both.  coef is the real coefficient a_t of eq. hamiltonian. */
+typedef struct {
+    uint64_t x, z;
+    double coef;
+} svq_pauli;
+
+typedef struct {
+    int32_t n_qr;            /* qubit reorderings executed (eq. n_qr) */
+    int32_t n_gate_passes;   /* fused gate passes, one HBM read+write each */
+    int32_t n_evc_passes;    /* read-only Pauli passes */
+    int32_t n_groups;        /* X/Y flip-mask groups of the Hamiltonian */
+    int32_t n_phases;        /* register phases over all passes */
+    int32_t tile_k;          /* tile width used (bits) */
+    double bytes;            /* algorithmic HBM bytes of the launched passes */
+    double ms_plan;          /* host planning time, 0 when the plan was cached */
+} svq_stats;
+
+/* Create a state of n qubits (1 <= n <= 34), g emulated global qubits
+ * (0 <= g < n, n - g >= 10), dtype c64 (float2, FP32 arithmetic) or c128
+ * (double2).  dev_buf: borrowed device buffer of >= 2^n * 8 (c64) or 16
+ * (c128) bytes that must outlive the handle, or NULL to let the library
+ * allocate (and free on destroy).  The state starts as |0...0> with
+ * pos[q] = q.  Errors: EINVAL (n, g, dtype), ESHAPE (buf_bytes), ENOMEM,
+ * EHIP. */
+svq_status sv_create(int n, int g, svq_dtype dtype, void *dev_buf, size_t buf_bytes,
+                     void *stream, svq_state *out);
+svq_status sv_destroy(svq_state st);
+
+/* Set the logical basis state |index>, resetting the layout to pos[q] = q. */
+svq_status sv_set_basis(svq_state st, uint64_t index);
+
+/* Copy a host array of 2^n amplitudes in logical order (complex64 or
+ * complex128 as the handle's dtype) into the state; layout reset to
+ * identity. */
+svq_status sv_set_amplitudes(svq_state st, const void *host_logical);
+
+/* Copy the state to a host array in logical order.  May reorder the device
+ * buffer back to the identity layout first (the logical state is kept). */
+svq_status sv_get_amplitudes(svq_state st, void *host_logical);
+
+/* Physical position of every logical qubit (pos_out[n]). */
+svq_status sv_get_layout(svq_state st, int32_t *pos_out);
+
+/* Device pointer of the amplitude buffer (physical order). */
+svq_status sv_device_ptr(svq_state st, void **ptr_out);
+
+/* QSU (eq. update_sv_gate): psi <- U_{m-1} ... U_0 psi, run under the given
+ * schedule.  LAZY uses flat time-space tiling (Algs. 1-3, Section "Flat
+ * tiling") over the chunk-local qubits, then packs each QR tile's gates into
+ * LDS-resident passes of 2^tile_k amplitudes.  EAGER reorders on every wide
+ * gate in breadth-first order.  tile_k = 0 picks the tuned width.  theta may
+ * be NULL when no gate has param >= 0.  Plans are cached per (gates'
+ * structure, n, g, layout, schedule, tile); angles are re-read every call.
+ * Errors: EINVAL (kind, qubits, param, non-finite angle), EHIP. */
+svq_status sv_apply_circuit(svq_state st, const svq_gate *gates, int m, const double *theta,
+                            int n_theta, svq_sched sched, int tile_k, svq_stats *stats);
+
+/* Reorder to a new layout: new_pos[q] = physical bit of logical qubit q (a
+ * permutation of 0..n-1).  An involutive relayout (a set of disjoint bit
+ * transpositions, as every QR of Section "Qubit reordering" is) runs as one
+ * in-place pass that touches only the fraction 1 - 2^{-s} of elements whose
+ * exchanged bits differ; any other permutation runs as two such passes. */
+svq_status sv_qr_permute(svq_state st, const int32_t *new_pos);
+
+/* EVC (eq. evc): E = sum_t a_t <psi|P_t|psi>.  Pauli strings are grouped by
+ * X/Y mask; LAZY tiles the groups with Alg. 6 using diagonalization (only the
+ * X/Y sites must be local, eq. without_QR / eq. par_exp), EAGER visits terms
+ * in index order and reorders as needed.  Per-chunk partial sums E_j (eq.
+ * local_evc) are reduced in FP64 (eq. aggregation).  energy_host (sync) and/or
+ * energy_dev (device double, async on the stream) receive E; chunk_dev
+ * (nullable, 2^g doubles) receives the per-chunk sums.  Errors: EINVAL
+ * (masks >= 2^n, non-finite coefficient), EHIP. */
+svq_status sv_expectation(svq_state st, const svq_pauli *terms, int n_terms, svq_sched sched,
+                          double *energy_host, double *energy_dev, double *chunk_dev,
+                          svq_stats *stats);
+
+/* H|psi> into a second handle of the same shape (out).  FP64 accumulation. */
+svq_status sv_apply_hamiltonian(svq_state st, const svq_pauli *terms, int n_terms,
+                                svq_state out);
+
+/* Gradient of E(theta) = <psi0|U(theta)^dag H U(theta)|psi0> by the adjoint
+ * method: forward pass, lambda = H psi, then a reverse sweep that un-applies
+ * every gate on psi and lambda (no per-layer checkpoints) while summing
+ * dE/dt_j = 2 Im <lambda|K_j|psi> in FP64.  The handle's current state is
+ * psi0; on return it holds U(theta)psi0.  grad_host/grad_dev receive n_theta
+ * doubles, energy_host/energy_dev E.  Errors: as sv_apply_circuit. */
+svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *theta,
+                   int n_theta, const svq_pauli *terms, int n_terms, svq_sched sched,
+                   double *energy_host, double *energy_dev, double *grad_host,
+                   double *grad_dev, svq_stats *stats);
+
+/* Host-only planning (no GPU needed), for inspection and tests.
+ * Circuit: order_out[m] = gate index at each schedule position,
+ * qr_tile_out[m] = QR tile of each position, pass_out[m] = gate pass of each
+ * position, local_out[m] = bit mask of the local qubit set M(g(x)) at each
+ * position; *n_qr_out = reorderings (eq. n_qr), *n_pass_out = gate passes.
+ * Paulis (x-mask groups): order_out[nt], qr_tile_out[nt], pass_out[nt],
+ * local_out[nt] likewise.  tile_k/low_bits/reg_bits = 0 pick defaults. */
+svq_status sv_plan_circuit(int n, int g, const svq_gate *gates, int m, svq_sched sched,
+                           int tile_k, int32_t *order_out, int32_t *qr_tile_out,
+                           int32_t *pass_out, uint64_t *local_out, int32_t *n_qr_out,
+                           int32_t *n_pass_out);
+svq_status sv_plan_paulis(int n, int g, const svq_pauli *terms, int n_terms, svq_sched sched,
+                          int tile_k, int32_t *order_out, int32_t *qr_tile_out,
+                          int32_t *pass_out, uint64_t *local_out, int32_t *n_qr_out,
+                          int32_t *n_pass_out);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *sv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVQ_C_ABI_H */

@@ -1,0 +1,811 @@
+// C ABI of libsvq.so (declared in include/svq.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "svq.h"
+
+using namespace svq;
+
+namespace {
+
+thread_local std::string g_err;
+
+svq_status fail(svq_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= cap) return hipSuccess;
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+            cap = 0;
+        }
+        size_t want = std::max<size_t>(bytes, 256);
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+};
+
+struct CachedCircuit {
+    CircuitPlan plan;
+    DevBuf d_phases;
+    bool uploaded = false;
+};
+
+struct CachedPaulis {
+    PauliPlan plan;
+    std::vector<WideTerm> wide;
+    DevBuf d_groups, d_terms, d_hgroups, d_hterms, d_off, d_nblk, d_wide;
+    bool uploaded = false;
+};
+
+int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::atoi(v);
+}
+
+}  // namespace
+
+struct svq_state_s {
+    int n = 0, g = 0;
+    svq_dtype dtype = SVQ_C64;
+    void *buf = nullptr;
+    bool owns = false;
+    hipStream_t stream = nullptr;
+    std::vector<int> pos;
+    bool poisoned = false;
+    std::map<std::string, std::unique_ptr<CachedCircuit>> ccache;
+    std::map<std::string, std::unique_ptr<CachedPaulis>> pcache;
+    DevBuf d_ops, d_partials, d_chunks, d_extra, d_lam, d_gpart, d_pptr, d_pgate, d_energy, d_grad;
+    int device = 0;
+
+    bool dbl() const { return dtype == SVQ_C128; }
+    size_t esz() const { return dbl() ? 16 : 8; }
+    uint64_t N() const { return 1ULL << n; }
+    size_t bytes() const { return (size_t)N() * esz(); }
+};
+
+namespace {
+
+svq_status hip_fail(svq_state st, hipError_t e, const char *what) {
+    if (st) st->poisoned = true;
+    return fail(SVQ_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(st, expr, what)                       \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_fail(st, _e, what); \
+    } while (0)
+
+int default_k(const svq_state_s *st) {
+    int k = env_int("SVQ_TILE_K", st->dbl() ? 12 : 12);
+    return std::max(8, std::min(13, std::min(k, st->n - st->g)));
+}
+
+int default_c(const svq_state_s *st) { return env_int("SVQ_LOW_BITS", 5); }
+
+// Build the launch arguments of one QR step (disjoint transpositions).
+QrArgs make_qr_args(int n, bool dbl, const std::vector<Transposition> &tr) {
+    QrArgs a;
+    std::memset(&a, 0, sizeof(a));
+    int partner[64];
+    for (int i = 0; i < 64; ++i) partner[i] = -1;
+    for (const auto &t : tr) {
+        partner[t.a] = t.b;
+        partner[t.b] = t.a;
+    }
+    const int clow = std::min(n, dbl ? 5 : 6);
+    const int target = std::min(n, 10);
+    uint64_t T = 0;
+    for (int b = 0; b < clow; ++b) {
+        T |= 1ULL << b;
+        if (partner[b] >= 0) T |= 1ULL << partner[b];
+    }
+    for (int b = 0; b < n && __builtin_popcountll(T) < target; ++b)
+        if (!((T >> b) & 1) && partner[b] < 0) T |= 1ULL << b;
+    int j = 0;
+    int tl[64];
+    for (int b = 0; b < 64; ++b) tl[b] = -1;
+    for (int b = 0; b < n; ++b)
+        if ((T >> b) & 1) {
+            tl[b] = j;
+            a.tphys[j++] = (int8_t)b;
+        }
+    a.tbits = j;
+    a.ntiles = 1ULL << (n - j);
+    for (const auto &t : tr) {
+        const bool ia = (T >> t.a) & 1, ib = (T >> t.b) & 1;
+        if (ia && ib) {
+            a.inner[2 * a.ninner] = (int8_t)tl[t.a];
+            a.inner[2 * a.ninner + 1] = (int8_t)tl[t.b];
+            a.ninner++;
+        } else {
+            a.outer[2 * a.nouter] = (int8_t)t.a;
+            a.outer[2 * a.nouter + 1] = (int8_t)t.b;
+            a.nouter++;
+        }
+    }
+    return a;
+}
+
+void apply_transpositions(std::vector<int> &pos, const std::vector<Transposition> &tr) {
+    for (const auto &t : tr)
+        for (auto &p : pos) {
+            if (p == t.a) p = t.b;
+            else if (p == t.b) p = t.a;
+        }
+}
+
+double qr_bytes(const svq_state_s *st, const std::vector<Transposition> &tr) {
+    return 2.0 * (1.0 - std::ldexp(1.0, -(int)tr.size())) * (double)st->bytes();
+}
+
+svq_status run_qr(svq_state st, void *buf, const std::vector<Transposition> &tr) {
+    if (tr.empty()) return SVQ_OK;
+    QrArgs a = make_qr_args(st->n, st->dbl(), tr);
+    HIPCHK(st, launch_qr(st->dbl(), buf, a, st->stream), "qr_permute");
+    return SVQ_OK;
+}
+
+// Split an arbitrary relayout (physical p -> sigma[p]) into two involutions.
+void split_relayout(const std::vector<int> &sigma, std::vector<Transposition> &t1,
+                    std::vector<Transposition> &t2) {
+    const int n = (int)sigma.size();
+    std::vector<char> seen(n, 0);
+    for (int s = 0; s < n; ++s) {
+        if (seen[s]) continue;
+        std::vector<int> cyc;
+        for (int p = s; !seen[p]; p = sigma[p]) {
+            seen[p] = 1;
+            cyc.push_back(p);
+        }
+        const int L = (int)cyc.size();
+        if (L == 1) continue;
+        if (L == 2) {
+            t1.push_back({cyc[0], cyc[1]});
+            continue;
+        }
+        // sigma(c_i) = c_{i+1} = tau2(tau1(c_i)) with the involutions
+        // tau1: c_i <-> c_{-i} and tau2: c_i <-> c_{1-i} (indices mod L).
+        for (int i = 0; i < L; ++i) {
+            const int j1 = (L - i) % L;
+            if (i < j1) t1.push_back({cyc[i], cyc[j1]});
+            const int j2 = ((1 - i) % L + L) % L;
+            if (i < j2) t2.push_back({cyc[i], cyc[j2]});
+        }
+    }
+}
+
+svq_status relayout(svq_state st, void *buf, std::vector<int> &pos, const std::vector<int> &newpos) {
+    const int n = st->n;
+    std::vector<int> sigma(n);
+    for (int q = 0; q < n; ++q) sigma[pos[q]] = newpos[q];
+    std::vector<Transposition> t1, t2;
+    split_relayout(sigma, t1, t2);
+    svq_status s = run_qr(st, buf, t1);
+    if (s) return s;
+    apply_transpositions(pos, t1);
+    s = run_qr(st, buf, t2);
+    if (s) return s;
+    apply_transpositions(pos, t2);
+    return SVQ_OK;
+}
+
+std::string circuit_key(const std::vector<GateN> &gates, const svq_state_s *st, svq_sched sched,
+                        int k, int c, int rb, bool adj) {
+    std::string key;
+    auto put = [&](const void *p, size_t nb) { key.append((const char *)p, nb); };
+    int hdr[7] = {st->n, st->g, (int)sched, k, c, rb, adj ? 1 : 0};
+    put(hdr, sizeof(hdr));
+    for (int p : st->pos) put(&p, sizeof(p));
+    for (const auto &g : gates) {
+        int v[4] = {g.kind, g.q[0], g.q[1], g.param >= 0 ? 1 : 0};
+        put(v, sizeof(v));
+    }
+    return key;
+}
+
+svq_status get_circuit_plan(svq_state st, const std::vector<GateN> &gates, svq_sched sched,
+                            int k, bool adj, CachedCircuit **out, double *ms_plan) {
+    const int c = default_c(st);
+    const int rb = gate_rb(k);
+    std::string key = circuit_key(gates, st, sched, k, c, rb, adj);
+    auto it = st->ccache.find(key);
+    if (it != st->ccache.end()) {
+        *out = it->second.get();
+        *ms_plan = 0.0;
+        return SVQ_OK;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    auto cc = std::make_unique<CachedCircuit>();
+    std::string err = plan_circuit(st->n, st->g, gates, sched, k, rb, c, st->pos, cc->plan);
+    if (!err.empty()) return fail(SVQ_EINVAL, err);
+    auto t1 = std::chrono::steady_clock::now();
+    *ms_plan = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    HIPCHK(st, cc->d_phases.ensure(sizeof(PhaseDesc) * std::max<size_t>(1, cc->plan.phases.size())),
+           "alloc phases");
+    HIPCHK(st, hipMemcpyAsync(cc->d_phases.p, cc->plan.phases.data(),
+                              sizeof(PhaseDesc) * cc->plan.phases.size(), hipMemcpyHostToDevice,
+                              st->stream),
+           "upload phases");
+    if (st->ccache.size() > 64) st->ccache.clear();
+    *out = cc.get();
+    st->ccache[key] = std::move(cc);
+    return SVQ_OK;
+}
+
+svq_status check_state(svq_state st) {
+    if (!st) return fail(SVQ_EINVAL, "null handle");
+    if (st->poisoned) return fail(SVQ_EPOISONED, "handle poisoned by an earlier HIP failure");
+    HIPCHK(st, hipSetDevice(st->device), "hipSetDevice");
+    return SVQ_OK;
+}
+
+svq_status check_theta(const std::vector<GateN> &gates, const double *theta, int n_theta) {
+    bool any = false;
+    for (const auto &g : gates) any |= g.param >= 0;
+    if (any && !theta) return fail(SVQ_EINVAL, "theta is NULL but gates reference parameters");
+    for (int i = 0; i < n_theta && theta; ++i)
+        if (!std::isfinite(theta[i])) return fail(SVQ_EINVAL, "non-finite theta");
+    return SVQ_OK;
+}
+
+// Forward circuit application with an existing plan.
+svq_status run_circuit(svq_state st, CachedCircuit *cc, const std::vector<GateN> &gates,
+                       const double *theta, svq_stats *stats) {
+    CircuitPlan &P = cc->plan;
+    std::vector<OpDesc> ops = P.ops;
+    fill_ops(gates, theta, P.op_gate, ops, false);
+    HIPCHK(st, st->d_ops.ensure(sizeof(OpDesc) * std::max<size_t>(1, ops.size())), "alloc ops");
+    HIPCHK(st, hipMemcpyAsync(st->d_ops.p, ops.data(), sizeof(OpDesc) * ops.size(),
+                              hipMemcpyHostToDevice, st->stream),
+           "upload ops");
+    double bytes = 0.0;
+    for (const Step &s : P.steps) {
+        if (s.type == 0) {
+            svq_status r = run_qr(st, st->buf, s.qr);
+            if (r) return r;
+            bytes += qr_bytes(st, s.qr);
+        } else {
+            const PassArgs &a = P.passes[s.idx];
+            HIPCHK(st, launch_gate_pass(st->dbl(), P.k, false, st->buf, nullptr, a,
+                                        (const PhaseDesc *)cc->d_phases.p,
+                                        (const OpDesc *)st->d_ops.p, nullptr, a.nblocks,
+                                        st->stream),
+                   "gate_pass");
+            bytes += 2.0 * (double)st->bytes();
+        }
+    }
+    st->pos = P.pos_after;
+    if (stats) {
+        stats->n_qr += P.n_qr;
+        stats->n_gate_passes += (int)P.passes.size();
+        stats->n_phases += P.n_phases_total;
+        stats->tile_k = P.k;
+        stats->bytes += bytes;
+    }
+    return SVQ_OK;
+}
+
+std::string pauli_key(const svq_pauli *terms, int nt, const svq_state_s *st, svq_sched sched,
+                      int k, int c) {
+    std::string key;
+    int hdr[5] = {st->n, st->g, (int)sched, k, c};
+    key.append((const char *)hdr, sizeof(hdr));
+    for (int p : st->pos) key.append((const char *)&p, sizeof(p));
+    key.append((const char *)terms, sizeof(svq_pauli) * (size_t)nt);
+    return key;
+}
+
+svq_status get_pauli_plan(svq_state st, const svq_pauli *terms, int nt, svq_sched sched,
+                          CachedPaulis **out, double *ms_plan) {
+    const int k = default_k(st);
+    const int c = default_c(st);
+    std::string key = pauli_key(terms, nt, st, sched, k, c);
+    auto it = st->pcache.find(key);
+    if (it != st->pcache.end()) {
+        *out = it->second.get();
+        *ms_plan = 0.0;
+        return SVQ_OK;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    auto cp = std::make_unique<CachedPaulis>();
+    std::string err = plan_paulis(st->n, st->g, terms, nt, sched, k, c, 8, st->pos, cp->plan);
+    if (!err.empty()) return fail(SVQ_EINVAL, err);
+    PauliPlan &P = cp->plan;
+    // wide groups are evaluated directly in the final layout
+    for (int gi : P.wide_groups)
+        for (int t : P.group_terms[gi]) {
+            WideTerm w;
+            std::memset(&w, 0, sizeof(w));
+            uint64_t x = 0, z = 0;
+            for (int q = 0; q < st->n; ++q) {
+                if ((terms[t].x >> q) & 1) x |= 1ULL << P.pos_after[q];
+                if ((terms[t].z >> q) & 1) z |= 1ULL << P.pos_after[q];
+            }
+            w.x = x;
+            w.z = z;
+            w.coef = terms[t].coef;
+            w.ny = __builtin_popcountll(terms[t].x & terms[t].z);
+            cp->wide.push_back(w);
+        }
+    auto t1 = std::chrono::steady_clock::now();
+    *ms_plan = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    auto up = [&](DevBuf &b, const void *src, size_t nb) -> hipError_t {
+        hipError_t e = b.ensure(std::max<size_t>(nb, 64));
+        if (e != hipSuccess) return e;
+        if (nb) e = hipMemcpyAsync(b.p, src, nb, hipMemcpyHostToDevice, st->stream);
+        return e;
+    };
+    std::vector<int> off, nblk;
+    for (const auto &pa : P.passes) {
+        off.push_back(pa.part0);
+        nblk.push_back(pa.nblocks);
+    }
+    HIPCHK(st, up(cp->d_groups, P.groups.data(), sizeof(EvcGroup) * P.groups.size()), "upload groups");
+    HIPCHK(st, up(cp->d_terms, P.terms.data(), sizeof(EvcTerm) * P.terms.size()), "upload terms");
+    HIPCHK(st, up(cp->d_hgroups, P.hgroups.data(), sizeof(HpsiGroup) * P.hgroups.size()), "upload hgroups");
+    HIPCHK(st, up(cp->d_hterms, P.hterms.data(), sizeof(HpsiTerm) * P.hterms.size()), "upload hterms");
+    HIPCHK(st, up(cp->d_off, off.data(), sizeof(int) * off.size()), "upload offsets");
+    HIPCHK(st, up(cp->d_nblk, nblk.data(), sizeof(int) * nblk.size()), "upload nblk");
+    HIPCHK(st, up(cp->d_wide, cp->wide.data(), sizeof(WideTerm) * cp->wide.size()), "upload wide");
+    // keep host copies alive until the async copies ran
+    HIPCHK(st, hipStreamSynchronize(st->stream), "sync");
+    if (st->pcache.size() > 16) st->pcache.clear();
+    *out = cp.get();
+    st->pcache[key] = std::move(cp);
+    return SVQ_OK;
+}
+
+svq_status run_expectation(svq_state st, CachedPaulis *cp, double *energy_dev, double *chunk_dev,
+                           svq_stats *stats) {
+    PauliPlan &P = cp->plan;
+    const int nchunk = 1 << st->g;
+    HIPCHK(st, st->d_partials.ensure(sizeof(double) * std::max(1, P.total_blocks)), "alloc partials");
+    HIPCHK(st, st->d_chunks.ensure(sizeof(double) * nchunk), "alloc chunks");
+    const int dgrid = direct_grid(st->N());
+    HIPCHK(st, st->d_extra.ensure(sizeof(double) * dgrid), "alloc extra");
+    double bytes = 0.0;
+    for (const Step &s : P.steps) {
+        if (s.type == 0) {
+            svq_status r = run_qr(st, st->buf, s.qr);
+            if (r) return r;
+            bytes += qr_bytes(st, s.qr);
+        } else {
+            const EvcPassArgs &a = P.passes[s.idx];
+            HIPCHK(st, launch_evc_pass(st->dbl(), P.k, st->buf, a, (const EvcGroup *)cp->d_groups.p,
+                                       (const EvcTerm *)cp->d_terms.p, (double *)st->d_partials.p,
+                                       st->stream),
+                   "evc_pass");
+            bytes += (double)st->bytes();
+        }
+    }
+    int nextra = 0;
+    if (!cp->wide.empty()) {
+        HIPCHK(st, launch_evc_direct(st->dbl(), st->buf, st->N(), (const WideTerm *)cp->d_wide.p,
+                                     (int)cp->wide.size(), (double *)st->d_extra.p, st->stream),
+               "evc_direct");
+        nextra = dgrid;
+        bytes += 2.0 * (double)st->bytes();
+    }
+    double *chunks = chunk_dev ? chunk_dev : (double *)st->d_chunks.p;
+    HIPCHK(st, launch_reduce_chunks((const double *)st->d_partials.p, (const int *)cp->d_off.p,
+                                    (const int *)cp->d_nblk.p, (int)P.passes.size(), nchunk, chunks,
+                                    st->stream),
+           "reduce");
+    HIPCHK(st, launch_finish_energy(chunks, nchunk, (const double *)st->d_extra.p, nextra, energy_dev,
+                                    st->stream),
+           "finish");
+    st->pos = P.pos_after;
+    if (stats) {
+        stats->n_qr += P.n_qr;
+        stats->n_evc_passes += (int)P.passes.size();
+        stats->n_groups += (int)P.group_x.size();
+        stats->bytes += bytes;
+    }
+    return SVQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sv_last_error(void) { return g_err.c_str(); }
+
+svq_status sv_create(int n, int g, svq_dtype dtype, void *dev_buf, size_t buf_bytes, void *stream,
+                     svq_state *out) {
+    if (!out) return fail(SVQ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > 34) return fail(SVQ_EINVAL, "n must be in [1, 34]");
+    if (g < 0 || g >= n) return fail(SVQ_EINVAL, "g must be in [0, n)");
+    if (n - g < 8) return fail(SVQ_EINVAL, "need at least 8 chunk-local qubits (n - g >= 8)");
+    if (dtype != SVQ_C64 && dtype != SVQ_C128) return fail(SVQ_EINVAL, "bad dtype");
+    auto st = std::make_unique<svq_state_s>();
+    st->n = n;
+    st->g = g;
+    st->dtype = dtype;
+    st->stream = (hipStream_t)stream;
+    st->pos.resize(n);
+    for (int q = 0; q < n; ++q) st->pos[q] = q;
+    hipError_t e = hipGetDevice(&st->device);
+    if (e != hipSuccess) return fail(SVQ_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev_buf) {
+        if (buf_bytes < st->bytes()) return fail(SVQ_ESHAPE, "buffer smaller than 2^n amplitudes");
+        st->buf = dev_buf;
+        st->owns = false;
+    } else {
+        e = hipMalloc(&st->buf, st->bytes());
+        if (e != hipSuccess) return fail(SVQ_ENOMEM, std::string("hipMalloc state: ") + hipGetErrorString(e));
+        st->owns = true;
+    }
+    e = launch_fill_basis(st->dbl(), st->buf, st->N(), 0, st->stream);
+    if (e != hipSuccess) {
+        if (st->owns) (void)hipFree(st->buf);
+        return fail(SVQ_EHIP, std::string("init: ") + hipGetErrorString(e));
+    }
+    *out = st.release();
+    return SVQ_OK;
+}
+
+svq_status sv_destroy(svq_state st) {
+    if (!st) return fail(SVQ_EINVAL, "null handle");
+    (void)hipSetDevice(st->device);
+    (void)hipStreamSynchronize(st->stream);
+    if (st->owns && st->buf) (void)hipFree(st->buf);
+    delete st;
+    return SVQ_OK;
+}
+
+svq_status sv_set_basis(svq_state st, uint64_t index) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    if (index >= st->N()) return fail(SVQ_EINVAL, "basis index >= 2^n");
+    HIPCHK(st, launch_fill_basis(st->dbl(), st->buf, st->N(), index, st->stream), "fill_basis");
+    for (int q = 0; q < st->n; ++q) st->pos[q] = q;
+    return SVQ_OK;
+}
+
+svq_status sv_set_amplitudes(svq_state st, const void *host) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    if (!host) return fail(SVQ_EINVAL, "host is NULL");
+    HIPCHK(st, hipMemcpyAsync(st->buf, host, st->bytes(), hipMemcpyHostToDevice, st->stream), "H2D");
+    HIPCHK(st, hipStreamSynchronize(st->stream), "sync");
+    for (int q = 0; q < st->n; ++q) st->pos[q] = q;
+    return SVQ_OK;
+}
+
+svq_status sv_get_amplitudes(svq_state st, void *host) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    if (!host) return fail(SVQ_EINVAL, "host is NULL");
+    std::vector<int> ident(st->n);
+    for (int q = 0; q < st->n; ++q) ident[q] = q;
+    s = relayout(st, st->buf, st->pos, ident);
+    if (s) return s;
+    HIPCHK(st, hipMemcpyAsync(host, st->buf, st->bytes(), hipMemcpyDeviceToHost, st->stream), "D2H");
+    HIPCHK(st, hipStreamSynchronize(st->stream), "sync");
+    return SVQ_OK;
+}
+
+svq_status sv_get_layout(svq_state st, int32_t *pos_out) {
+    if (!st) return fail(SVQ_EINVAL, "null handle");
+    if (!pos_out) return fail(SVQ_EINVAL, "pos_out is NULL");
+    for (int q = 0; q < st->n; ++q) pos_out[q] = st->pos[q];
+    return SVQ_OK;
+}
+
+svq_status sv_device_ptr(svq_state st, void **ptr_out) {
+    if (!st || !ptr_out) return fail(SVQ_EINVAL, "null argument");
+    *ptr_out = st->buf;
+    return SVQ_OK;
+}
+
+svq_status sv_apply_circuit(svq_state st, const svq_gate *gates, int m, const double *theta,
+                            int n_theta, svq_sched sched, int tile_k, svq_stats *stats) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    if (m < 0 || (m > 0 && !gates) || n_theta < 0) return fail(SVQ_EINVAL, "bad gate list");
+    if (sched != SVQ_EAGER && sched != SVQ_LAZY) return fail(SVQ_EINVAL, "bad schedule");
+    if (tile_k != 0 && (tile_k < 8 || tile_k > 13)) return fail(SVQ_EINVAL, "tile_k must be 0 or in [8, 13]");
+    std::vector<GateN> gn;
+    std::string err = normalize_gates(st->n, gates, m, n_theta, gn);
+    if (!err.empty()) return fail(SVQ_EINVAL, err);
+    s = check_theta(gn, theta, n_theta);
+    if (s) return s;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (m == 0) return SVQ_OK;
+    const int k = tile_k ? std::min(tile_k, st->n - st->g) : default_k(st);
+    CachedCircuit *cc = nullptr;
+    double ms = 0;
+    s = get_circuit_plan(st, gn, sched, k, false, &cc, &ms);
+    if (s) return s;
+    if (stats) stats->ms_plan = ms;
+    return run_circuit(st, cc, gn, theta, stats);
+}
+
+svq_status sv_qr_permute(svq_state st, const int32_t *new_pos) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    if (!new_pos) return fail(SVQ_EINVAL, "new_pos is NULL");
+    std::vector<int> np(st->n);
+    std::vector<char> seen(st->n, 0);
+    for (int q = 0; q < st->n; ++q) {
+        if (new_pos[q] < 0 || new_pos[q] >= st->n || seen[new_pos[q]])
+            return fail(SVQ_EINVAL, "new_pos is not a permutation of 0..n-1");
+        seen[new_pos[q]] = 1;
+        np[q] = new_pos[q];
+    }
+    return relayout(st, st->buf, st->pos, np);
+}
+
+svq_status sv_expectation(svq_state st, const svq_pauli *terms, int n_terms, svq_sched sched,
+                          double *energy_host, double *energy_dev, double *chunk_dev,
+                          svq_stats *stats) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    if (n_terms < 0 || (n_terms > 0 && !terms)) return fail(SVQ_EINVAL, "bad term list");
+    if (sched != SVQ_EAGER && sched != SVQ_LAZY) return fail(SVQ_EINVAL, "bad schedule");
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    CachedPaulis *cp = nullptr;
+    double ms = 0;
+    s = get_pauli_plan(st, terms, n_terms, sched, &cp, &ms);
+    if (s) return s;
+    if (stats) stats->ms_plan = ms;
+    HIPCHK(st, st->d_energy.ensure(sizeof(double)), "alloc energy");
+    double *edev = energy_dev ? energy_dev : (double *)st->d_energy.p;
+    s = run_expectation(st, cp, edev, chunk_dev, stats);
+    if (s) return s;
+    if (stats) stats->tile_k = cp->plan.k;
+    if (energy_host) {
+        HIPCHK(st, hipMemcpyAsync(energy_host, edev, sizeof(double), hipMemcpyDeviceToHost, st->stream), "D2H");
+        HIPCHK(st, hipStreamSynchronize(st->stream), "sync");
+    }
+    return SVQ_OK;
+}
+
+svq_status sv_apply_hamiltonian(svq_state st, const svq_pauli *terms, int n_terms, svq_state out) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    if (!out || out->n != st->n || out->g != st->g || out->dtype != st->dtype)
+        return fail(SVQ_ESHAPE, "output handle shape differs");
+    if (n_terms < 0 || (n_terms > 0 && !terms)) return fail(SVQ_EINVAL, "bad term list");
+    CachedPaulis *cp = nullptr;
+    double ms = 0;
+    s = get_pauli_plan(st, terms, n_terms, SVQ_LAZY, &cp, &ms);
+    if (s) return s;
+    PauliPlan &P = cp->plan;
+    // out follows psi's layout; its old content is overwritten
+    const int TPBH = hpsi_tpb(P.k);
+    int nblocks = 1 << (st->n - P.k);
+    (void)TPBH;
+    bool any = false;
+    for (const Step &stp : P.steps) {
+        if (stp.type == 0) {
+            s = run_qr(st, st->buf, stp.qr);
+            if (s) return s;
+            s = run_qr(st, out->buf, stp.qr);
+            if (s) return s;
+        } else {
+            HpsiPassArgs a = P.hpasses[stp.idx];
+            a.accumulate = any ? 1 : 0;
+            HIPCHK(st, launch_hpsi_pass(st->dbl(), P.k, nblocks, st->buf, out->buf, a,
+                                        (const HpsiGroup *)cp->d_hgroups.p,
+                                        (const HpsiTerm *)cp->d_hterms.p, st->stream),
+                   "hpsi_pass");
+            any = true;
+        }
+    }
+    if (!cp->wide.empty() || !any) {
+        HIPCHK(st, launch_hpsi_direct(st->dbl(), st->buf, out->buf, st->N(),
+                                      (const WideTerm *)cp->d_wide.p, (int)cp->wide.size(),
+                                      any ? 1 : 0, st->stream),
+               "hpsi_direct");
+    }
+    st->pos = P.pos_after;
+    out->pos = P.pos_after;
+    return SVQ_OK;
+}
+
+svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *theta, int n_theta,
+                   const svq_pauli *terms, int n_terms, svq_sched sched, double *energy_host,
+                   double *energy_dev, double *grad_host, double *grad_dev, svq_stats *stats) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    if (m < 0 || (m > 0 && !gates) || n_theta < 0) return fail(SVQ_EINVAL, "bad gate list");
+    if (n_terms < 0 || (n_terms > 0 && !terms)) return fail(SVQ_EINVAL, "bad term list");
+    if (sched != SVQ_EAGER && sched != SVQ_LAZY) return fail(SVQ_EINVAL, "bad schedule");
+    std::vector<GateN> gn;
+    std::string err = normalize_gates(st->n, gates, m, n_theta, gn);
+    if (!err.empty()) return fail(SVQ_EINVAL, err);
+    s = check_theta(gn, theta, n_theta);
+    if (s) return s;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    // two tiles must fit in LDS for the reverse sweep
+    int k = default_k(st);
+    if (st->dbl()) k = std::min(k, 12);
+    const std::vector<int> pos0 = st->pos;
+    CachedCircuit *cc = nullptr;
+    double ms = 0;
+    s = get_circuit_plan(st, gn, sched, k, true, &cc, &ms);
+    if (s) return s;
+    CircuitPlan &P = cc->plan;
+    // forward
+    s = run_circuit(st, cc, gn, theta, stats);
+    if (s) return s;
+    // lambda = H psi (lambda buffer follows psi's layout)
+    HIPCHK(st, st->d_lam.ensure(st->bytes()), "alloc lambda");
+    svq_state_s lam_view;
+    lam_view.n = st->n;
+    lam_view.g = st->g;
+    lam_view.dtype = st->dtype;
+    lam_view.buf = st->d_lam.p;
+    lam_view.stream = st->stream;
+    lam_view.pos = st->pos;
+    lam_view.device = st->device;
+    s = sv_apply_hamiltonian(st, terms, n_terms, &lam_view);
+    lam_view.buf = nullptr;   // not owned
+    if (s) return s;
+    // E = Re <psi|lambda>
+    const int dg = dot_grid(st->N());
+    HIPCHK(st, st->d_extra.ensure(sizeof(double) * dg), "alloc extra");
+    HIPCHK(st, st->d_energy.ensure(sizeof(double)), "alloc energy");
+    double *edev = energy_dev ? energy_dev : (double *)st->d_energy.p;
+    HIPCHK(st, launch_dot_re(st->dbl(), st->buf, st->d_lam.p, st->N(), (double *)st->d_extra.p, st->stream), "dot");
+    HIPCHK(st, launch_sum((const double *)st->d_extra.p, dg, edev, st->stream), "sum");
+    // back to the circuit's final layout (both states)
+    {
+        std::vector<int> lp = st->pos;
+        s = relayout(st, st->d_lam.p, lp, P.pos_after);
+        if (s) return s;
+        s = relayout(st, st->buf, st->pos, P.pos_after);
+        if (s) return s;
+    }
+    // reverse sweep
+    std::vector<OpDesc> inv = P.ops;
+    fill_ops(gn, theta, P.op_gate, inv, true);
+    for (size_t i = 0; i < inv.size(); ++i) {
+        const GateN &g = gn[P.op_gate[i]];
+        inv[i].gslot = (g.param >= 0 && inv[i].gtype != GEN_NONE) ? P.op_gate[i] : -1;
+        if (inv[i].gslot < 0) inv[i].gtype = GEN_NONE;
+    }
+    HIPCHK(st, st->d_ops.ensure(sizeof(OpDesc) * std::max<size_t>(1, inv.size())), "alloc ops");
+    HIPCHK(st, hipMemcpyAsync(st->d_ops.p, inv.data(), sizeof(OpDesc) * inv.size(),
+                              hipMemcpyHostToDevice, st->stream),
+           "upload inverse ops");
+    const int nblocks = 1 << (st->n - P.k);
+    const int nwaves = (1 << (P.k - gate_rb(P.k))) / 64;
+    const int nper = nblocks * nwaves;
+    HIPCHK(st, st->d_gpart.ensure(sizeof(double) * (size_t)std::max(1, m) * nper), "alloc gpart");
+    for (auto it = P.steps.rbegin(); it != P.steps.rend(); ++it) {
+        if (it->type == 0) {
+            s = run_qr(st, st->buf, it->qr);
+            if (s) return s;
+            s = run_qr(st, st->d_lam.p, it->qr);
+            if (s) return s;
+        } else {
+            PassArgs a = P.passes[it->idx];
+            a.gslot_base = 0;
+            HIPCHK(st, launch_gate_pass(st->dbl(), P.k, true, st->buf, st->d_lam.p, a,
+                                        (const PhaseDesc *)cc->d_phases.p, (const OpDesc *)st->d_ops.p,
+                                        (double *)st->d_gpart.p, nblocks, st->stream),
+                   "adjoint_pass");
+        }
+    }
+    st->pos = pos0;
+    // gradient reduction: CSR param -> gates
+    std::vector<int> pptr(n_theta + 1, 0), pgate;
+    for (int i = 0; i < m; ++i)
+        if (gn[i].param >= 0 && (gn[i].kind == SVQ_RX || gn[i].kind == SVQ_RY || gn[i].kind == SVQ_RZ ||
+                                 gn[i].kind == SVQ_CPHASE || gn[i].kind == SVQ_GIVENS))
+            pptr[gn[i].param + 1]++;
+    for (int p = 0; p < n_theta; ++p) pptr[p + 1] += pptr[p];
+    pgate.resize(pptr[n_theta]);
+    {
+        std::vector<int> fillp(pptr.begin(), pptr.end() - 1);
+        for (int i = 0; i < m; ++i)
+            if (gn[i].param >= 0 && (gn[i].kind == SVQ_RX || gn[i].kind == SVQ_RY || gn[i].kind == SVQ_RZ ||
+                                     gn[i].kind == SVQ_CPHASE || gn[i].kind == SVQ_GIVENS))
+                pgate[fillp[gn[i].param]++] = i;
+    }
+    HIPCHK(st, st->d_pptr.ensure(sizeof(int) * pptr.size()), "alloc pptr");
+    HIPCHK(st, st->d_pgate.ensure(sizeof(int) * std::max<size_t>(1, pgate.size())), "alloc pgate");
+    HIPCHK(st, hipMemcpyAsync(st->d_pptr.p, pptr.data(), sizeof(int) * pptr.size(), hipMemcpyHostToDevice, st->stream), "upload pptr");
+    if (!pgate.empty())
+        HIPCHK(st, hipMemcpyAsync(st->d_pgate.p, pgate.data(), sizeof(int) * pgate.size(), hipMemcpyHostToDevice, st->stream), "upload pgate");
+    HIPCHK(st, st->d_grad.ensure(sizeof(double) * std::max(1, n_theta)), "alloc grad");
+    double *gdev = grad_dev ? grad_dev : (double *)st->d_grad.p;
+    HIPCHK(st, launch_grad_reduce((const double *)st->d_gpart.p, nper, (const int *)st->d_pptr.p,
+                                  (const int *)st->d_pgate.p, n_theta, gdev, st->stream),
+           "grad_reduce");
+    if (stats) {
+        stats->n_gate_passes += (int)P.passes.size();
+        stats->bytes += (double)P.passes.size() * 4.0 * (double)st->bytes();
+        stats->ms_plan += ms;
+    }
+    if (energy_host)
+        HIPCHK(st, hipMemcpyAsync(energy_host, edev, sizeof(double), hipMemcpyDeviceToHost, st->stream), "D2H");
+    if (grad_host && n_theta)
+        HIPCHK(st, hipMemcpyAsync(grad_host, gdev, sizeof(double) * n_theta, hipMemcpyDeviceToHost, st->stream), "D2H");
+    // pptr/pgate host vectors must outlive the async copies
+    HIPCHK(st, hipStreamSynchronize(st->stream), "sync");
+    return SVQ_OK;
+}
+
+static svq_status plan_common_circuit(int n, int g, const svq_gate *gates, int m, svq_sched sched,
+                                      int tile_k, CircuitPlan &P) {
+    if (n < 1 || n > 34 || g < 0 || g >= n || n - g < 8) return fail(SVQ_EINVAL, "bad n/g");
+    std::vector<GateN> gn;
+    std::string err = normalize_gates(n, gates, m, 1 << 30, gn);
+    if (!err.empty()) return fail(SVQ_EINVAL, err);
+    std::vector<int> pos(n);
+    for (int q = 0; q < n; ++q) pos[q] = q;
+    int k = tile_k ? tile_k : 12;
+    k = std::max(8, std::min(13, std::min(k, n - g)));
+    err = plan_circuit(n, g, gn, sched, k, gate_rb(k), env_int("SVQ_LOW_BITS", 5), pos, P);
+    if (!err.empty()) return fail(SVQ_EINVAL, err);
+    return SVQ_OK;
+}
+
+svq_status sv_plan_circuit(int n, int g, const svq_gate *gates, int m, svq_sched sched, int tile_k,
+                           int32_t *order_out, int32_t *qr_tile_out, int32_t *pass_out,
+                           uint64_t *local_out, int32_t *n_qr_out, int32_t *n_pass_out) {
+    CircuitPlan P;
+    svq_status s = plan_common_circuit(n, g, gates, m, sched, tile_k, P);
+    if (s) return s;
+    for (size_t i = 0; i < P.order.size(); ++i) {
+        if (order_out) order_out[i] = P.order[i];
+        if (qr_tile_out) qr_tile_out[i] = P.pos_qrtile[i];
+        if (pass_out) pass_out[i] = P.pos_pass[i];
+        if (local_out) local_out[i] = P.pos_local[i];
+    }
+    if (n_qr_out) *n_qr_out = P.n_qr;
+    if (n_pass_out) *n_pass_out = (int)P.passes.size();
+    return SVQ_OK;
+}
+
+svq_status sv_plan_paulis(int n, int g, const svq_pauli *terms, int n_terms, svq_sched sched,
+                          int tile_k, int32_t *order_out, int32_t *qr_tile_out, int32_t *pass_out,
+                          uint64_t *local_out, int32_t *n_qr_out, int32_t *n_pass_out) {
+    if (n < 1 || n > 34 || g < 0 || g >= n || n - g < 8) return fail(SVQ_EINVAL, "bad n/g");
+    std::vector<int> pos(n);
+    for (int q = 0; q < n; ++q) pos[q] = q;
+    int k = tile_k ? tile_k : 12;
+    k = std::max(8, std::min(13, std::min(k, n - g)));
+    PauliPlan P;
+    std::string err = plan_paulis(n, g, terms, n_terms, sched, k, env_int("SVQ_LOW_BITS", 5), 8, pos, P);
+    if (!err.empty()) return fail(SVQ_EINVAL, err);
+    for (size_t i = 0; i < P.order.size(); ++i) {
+        if (order_out) order_out[i] = P.order[i];
+        if (qr_tile_out) qr_tile_out[i] = P.pos_qrtile[i];
+        if (pass_out) pass_out[i] = P.pos_pass[i];
+        if (local_out) local_out[i] = P.pos_local[i];
+    }
+    if (n_qr_out) *n_qr_out = P.n_qr;
+    if (n_pass_out) *n_pass_out = (int)P.passes.size();
+    return SVQ_OK;
+}
+
+}  // extern "C"

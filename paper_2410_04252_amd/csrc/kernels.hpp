@@ -1,0 +1,56 @@
+// Host launch interface of the HIP kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "svq_dev.hpp"
+
+namespace svq {
+
+// In-place relayout by disjoint transpositions of physical bits.
+struct QrArgs {
+    int32_t tbits;          // tile bits
+    int32_t nouter;         // transpositions with both bits outside the tile
+    int32_t ninner;         // transpositions inside the tile (tile-local bits)
+    int32_t pad;
+    uint64_t ntiles;        // 2^(n - tbits)
+    int8_t tphys[16];       // physical bit of tile-local bit j (ascending)
+    int8_t outer[64];       // pairs (a, b) of physical bits
+    int8_t inner[32];       // pairs (a, b) of tile-local bits
+};
+
+struct WideTerm {
+    uint64_t x, z;          // physical masks
+    double coef;
+    int32_t ny;             // popcount(x & z)
+    int32_t pad;
+};
+
+hipError_t launch_gate_pass(bool dbl, int k, bool adj, void *psi, void *lam, const PassArgs &a,
+                            const PhaseDesc *ph, const OpDesc *ops, double *gpart, int nbt,
+                            hipStream_t s);
+hipError_t launch_qr(bool dbl, void *psi, const QrArgs &a, hipStream_t s);
+hipError_t launch_evc_pass(bool dbl, int k, const void *psi, const EvcPassArgs &a,
+                           const EvcGroup *g, const EvcTerm *t, double *part, hipStream_t s);
+hipError_t launch_hpsi_pass(bool dbl, int k, int nblocks, const void *psi, void *lam,
+                            const HpsiPassArgs &a, const HpsiGroup *g, const HpsiTerm *t,
+                            hipStream_t s);
+int direct_grid(uint64_t N);
+hipError_t launch_evc_direct(bool dbl, const void *psi, uint64_t N, const WideTerm *wt, int nw,
+                             double *part, hipStream_t s);
+hipError_t launch_hpsi_direct(bool dbl, const void *psi, void *lam, uint64_t N, const WideTerm *wt,
+                              int nw, int accumulate, hipStream_t s);
+hipError_t launch_reduce_chunks(const double *partials, const int *pass_off, const int *pass_nblk,
+                                int npass, int nchunk, double *chunk_out, hipStream_t s);
+hipError_t launch_finish_energy(const double *chunk, int nchunk, const double *extra, int nextra,
+                                double *out, hipStream_t s);
+hipError_t launch_sum(const double *in, int n, double *out, hipStream_t s);
+int dot_grid(uint64_t N);
+hipError_t launch_dot_re(bool dbl, const void *a, const void *b, uint64_t N, double *partials,
+                         hipStream_t s);
+hipError_t launch_grad_reduce(const double *gpart, int nper, const int *pptr, const int *pgate,
+                              int nparam, double *grad, hipStream_t s);
+hipError_t launch_fill_basis(bool dbl, void *psi, uint64_t N, uint64_t idx, hipStream_t s);
+
+}  // namespace svq

@@ -1,0 +1,965 @@
+// Host planner.  See plan.hpp for the three levels.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <thread>
+#include <unordered_map>
+
+namespace svq {
+
+static inline int popc(uint64_t v) { return __builtin_popcountll(v); }
+static inline uint64_t bit(int q) { return 1ULL << q; }
+
+// ---------------------------------------------------------------------------
+// gate normalisation
+// ---------------------------------------------------------------------------
+
+static int arity(int kind) {
+    switch (kind) {
+    case SVQ_CNOT: case SVQ_CZ: case SVQ_CPHASE: case SVQ_GIVENS: case SVQ_SWAP: case SVQ_U2:
+        return 2;
+    default:
+        return 1;
+    }
+}
+
+std::string normalize_gates(int n, const svq_gate *gates, int m, int n_theta,
+                            std::vector<GateN> &out) {
+    out.clear();
+    out.reserve(m);
+    for (int i = 0; i < m; ++i) {
+        const svq_gate &s = gates[i];
+        GateN g;
+        g.kind = s.kind;
+        if (s.kind < SVQ_H || s.kind > SVQ_U2) return "gate " + std::to_string(i) + ": bad kind";
+        g.nq = arity(s.kind);
+        for (int j = 0; j < g.nq; ++j) {
+            if (s.q[j] < 0 || s.q[j] >= n) return "gate " + std::to_string(i) + ": qubit out of range";
+            g.q[j] = s.q[j];
+        }
+        if (g.nq == 2 && g.q[0] == g.q[1]) return "gate " + std::to_string(i) + ": repeated qubit";
+        g.param = s.param;
+        if (s.param >= n_theta || s.param < -1)
+            return "gate " + std::to_string(i) + ": param index out of range";
+        bool parametric = s.kind == SVQ_RX || s.kind == SVQ_RY || s.kind == SVQ_RZ ||
+                          s.kind == SVQ_CPHASE || s.kind == SVQ_GIVENS;
+        if (!parametric && s.param >= 0) return "gate " + std::to_string(i) + ": kind takes no parameter";
+        g.angle = s.angle;
+        if (s.param < 0 && !std::isfinite(s.angle)) return "gate " + std::to_string(i) + ": non-finite angle";
+        if (s.kind == SVQ_U1 || s.kind == SVQ_U2) {
+            int cnt = s.kind == SVQ_U1 ? 8 : 32;
+            for (int j = 0; j < cnt; ++j) {
+                if (!std::isfinite(s.mat[j])) return "gate " + std::to_string(i) + ": non-finite matrix";
+                g.mat[j] = s.mat[j];
+            }
+        }
+        g.tmask = bit(g.q[0]) | (g.nq == 2 ? bit(g.q[1]) : 0);
+        switch (s.kind) {
+        case SVQ_Z: case SVQ_S: case SVQ_T: case SVQ_RZ:
+            g.diag_q = g.q[0];
+            break;
+        case SVQ_CZ: case SVQ_CPHASE:
+            g.diag_q = g.q[1];
+            g.ctrlmask = bit(g.q[0]);
+            break;
+        case SVQ_CNOT:
+            g.ctrlmask = bit(g.q[0]);
+            g.mixmask = bit(g.q[1]);
+            break;
+        case SVQ_GIVENS: case SVQ_SWAP: case SVQ_U2:
+            g.mixmask = g.tmask;
+            break;
+        default:
+            g.mixmask = bit(g.q[0]);
+        }
+        out.push_back(g);
+    }
+    return "";
+}
+
+// ---------------------------------------------------------------------------
+// level 1
+// ---------------------------------------------------------------------------
+
+std::vector<int> depth_order(const std::vector<uint64_t> &targets) {
+    const int m = (int)targets.size();
+    std::vector<int> depth(m);
+    int last[64];
+    for (int q = 0; q < 64; ++q) last[q] = -1;
+    for (int i = 0; i < m; ++i) {
+        int d = 0;
+        for (uint64_t t = targets[i]; t; t &= t - 1) {
+            int q = __builtin_ctzll(t);
+            d = std::max(d, last[q] + 1);
+        }
+        depth[i] = d;
+        for (uint64_t t = targets[i]; t; t &= t - 1) last[__builtin_ctzll(t)] = d;
+    }
+    // Bucket by depth (the paper's O(d m) bucket sort), then within a depth
+    // order by the ascending target tuple, then by index.
+    std::vector<int> order(m);
+    for (int i = 0; i < m; ++i) order[i] = i;
+    auto key_less = [&](int a, int b) {
+        if (depth[a] != depth[b]) return depth[a] < depth[b];
+        uint64_t ta = targets[a], tb = targets[b];
+        while (ta && tb) {   // compare ascending qubit tuples lexicographically
+            int qa = __builtin_ctzll(ta), qb = __builtin_ctzll(tb);
+            if (qa != qb) return qa < qb;
+            ta &= ta - 1;
+            tb &= tb - 1;
+        }
+        if (ta != tb) return ta == 0;   // a shorter tuple that is a prefix sorts first
+        return a < b;
+    };
+    std::stable_sort(order.begin(), order.end(), key_less);
+    return order;
+}
+
+// Alg. 2: greedy tile under local set QL.
+static std::vector<int> tile_construction(uint64_t QL, const std::vector<int> &remain,
+                                          const std::vector<uint64_t> &targets) {
+    uint64_t avail = QL;
+    std::vector<int> tile;
+    for (int i : remain) {
+        uint64_t T = targets[i];
+        if ((T & ~avail) == 0) tile.push_back(i);
+        else avail &= ~T;
+        if (!avail) break;
+    }
+    return tile;
+}
+
+// Alg. 3: greedy local-set choice from the shallowest remaining operators,
+// then the boundary fill with the lowest free qubits of `universe`.
+static uint64_t qubit_mapping(uint64_t universe, uint64_t init, const std::vector<int> &remain,
+                              const std::vector<uint64_t> &targets, int budget) {
+    uint64_t avail = universe;
+    uint64_t QL = init;
+    for (int i : remain) {
+        uint64_t T = targets[i];
+        if ((T & ~avail) == 0 && popc(QL | T) <= budget) QL |= T;
+        else avail &= ~T;
+        if (!avail) break;
+    }
+    for (uint64_t free = universe & ~QL; popc(QL) < budget && free; free &= free - 1)
+        QL |= free & (~free + 1);
+    return QL;
+}
+
+static uint64_t local_set(const std::vector<int> &pos, int nL) {
+    uint64_t s = 0;
+    for (size_t q = 0; q < pos.size(); ++q)
+        if (pos[q] < nL) s |= bit((int)q);
+    return s;
+}
+
+// Exchange outgoing local qubits with incoming global ones, pairing both in
+// ascending physical position; updates pos.
+static std::vector<Transposition> remap(std::vector<int> &pos, int nL, uint64_t newQL) {
+    const int n = (int)pos.size();
+    std::vector<int> out, in;
+    for (int q = 0; q < n; ++q) {
+        bool loc = pos[q] < nL, want = (newQL >> q) & 1;
+        if (loc && !want) out.push_back(q);
+        if (!loc && want) in.push_back(q);
+    }
+    auto by_pos = [&](int a, int b) { return pos[a] < pos[b]; };
+    std::sort(out.begin(), out.end(), by_pos);
+    std::sort(in.begin(), in.end(), by_pos);
+    std::vector<Transposition> tr;
+    for (size_t i = 0; i < out.size() && i < in.size(); ++i) {
+        tr.push_back({pos[out[i]], pos[in[i]]});
+        std::swap(pos[out[i]], pos[in[i]]);
+    }
+    return tr;
+}
+
+std::vector<L1Tile> flat_tiling(int n, int nL, const std::vector<uint64_t> &targets,
+                                std::vector<int> &pos) {
+    const uint64_t Q = n >= 64 ? ~0ULL : (bit(n) - 1);
+    std::vector<int> remain = depth_order(targets);
+    uint64_t QL = local_set(pos, nL);
+    std::vector<L1Tile> tiles;
+    bool first = true;
+    while (!remain.empty()) {
+        std::vector<Transposition> tr;
+        if (!first) {
+            QL = qubit_mapping(Q, 0, remain, targets, nL);
+            tr = remap(pos, nL, QL);
+        }
+        first = false;
+        std::vector<int> G = tile_construction(QL, remain, targets);
+        if (G.empty()) continue;   // (only possible on the first round)
+        std::vector<char> taken(targets.size(), 0);
+        for (int i : G) taken[i] = 1;
+        std::vector<int> rest;
+        for (int i : remain)
+            if (!taken[i]) rest.push_back(i);
+        remain.swap(rest);
+        if (!tiles.empty() && tiles.back().local == QL && tr.empty()) {
+            tiles.back().ops.insert(tiles.back().ops.end(), G.begin(), G.end());
+        } else {
+            L1Tile t;
+            t.local = QL;
+            t.ops = G;
+            t.qr = tr;
+            tiles.push_back(std::move(t));
+        }
+    }
+    return tiles;
+}
+
+std::vector<L1Tile> ad_hoc(int n, int nL, const std::vector<uint64_t> &targets,
+                           const std::vector<int> &order, std::vector<int> &pos) {
+    std::vector<L1Tile> tiles;
+    for (int i : order) {
+        uint64_t T = targets[i];
+        uint64_t local = local_set(pos, nL);
+        std::vector<Transposition> tr;
+        if (T & ~local) {
+            std::vector<int> in, cand;
+            for (int q = 0; q < n; ++q) {
+                if (((T >> q) & 1) && !((local >> q) & 1)) in.push_back(q);
+                if (((local >> q) & 1) && !((T >> q) & 1)) cand.push_back(q);
+            }
+            std::sort(in.begin(), in.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+            std::sort(cand.begin(), cand.end(), [&](int a, int b) { return pos[a] > pos[b]; });
+            cand.resize(in.size());
+            std::sort(cand.begin(), cand.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+            for (size_t j = 0; j < in.size(); ++j) {
+                tr.push_back({pos[cand[j]], pos[in[j]]});
+                std::swap(pos[cand[j]], pos[in[j]]);
+            }
+            local = local_set(pos, nL);
+        }
+        if (tiles.empty() || !tr.empty() || tiles.back().local != local) {
+            L1Tile t;
+            t.local = local;
+            t.qr = tr;
+            tiles.push_back(std::move(t));
+        }
+        tiles.back().ops.push_back(i);
+    }
+    return tiles;
+}
+
+std::vector<L1Tile> tiling_pauli(int n, int nL, const std::vector<uint64_t> &supports,
+                                 const std::vector<int> &weights, std::vector<int> &pos) {
+    // All n_L-subsets of {0..n-1} in lexicographic order of sorted tuples.
+    std::vector<uint64_t> sets;
+    {
+        std::vector<int> c(nL);
+        for (int i = 0; i < nL; ++i) c[i] = i;
+        while (true) {
+            uint64_t mk = 0;
+            for (int v : c) mk |= bit(v);
+            sets.push_back(mk);
+            int i = nL - 1;
+            while (i >= 0 && c[i] == n - nL + i) --i;
+            if (i < 0) break;
+            ++c[i];
+            for (int j = i + 1; j < nL; ++j) c[j] = c[j - 1] + 1;
+        }
+    }
+    std::vector<int> remain(supports.size());
+    for (size_t i = 0; i < supports.size(); ++i) remain[i] = (int)i;
+    std::vector<L1Tile> tiles;
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    uint64_t cur = local_set(pos, nL);
+    while (!remain.empty()) {
+        std::vector<uint64_t> rs(remain.size());
+        std::vector<int> rw(remain.size());
+        for (size_t i = 0; i < remain.size(); ++i) {
+            rs[i] = supports[remain[i]];
+            rw[i] = weights[remain[i]];
+        }
+        auto count = [&](uint64_t mk) {
+            long long c = 0;
+            for (size_t i = 0; i < rs.size(); ++i)
+                if ((rs[i] & ~mk) == 0) c += rw[i];
+            return c;
+        };
+        // Per-thread best over a contiguous slice, strict '<' keeps the first.
+        std::vector<long long> bestc(nth, 0);
+        std::vector<long long> besti(nth, -1);
+        std::vector<std::thread> th;
+        const size_t ns = sets.size();
+        for (unsigned t = 0; t < nth; ++t) {
+            th.emplace_back([&, t]() {
+                size_t lo = ns * t / nth, hi = ns * (t + 1) / nth;
+                long long bc = 0, bi = -1;
+                for (size_t s = lo; s < hi; ++s) {
+                    long long c = count(sets[s]);
+                    if (bc < c) { bc = c; bi = (long long)s; }
+                }
+                bestc[t] = bc;
+                besti[t] = bi;
+            });
+        }
+        for (auto &x : th) x.join();
+        long long bc = count(cur);
+        uint64_t best = cur;
+        if (bc == 0) best = 0;
+        for (unsigned t = 0; t < nth; ++t)
+            if (bc < bestc[t]) { bc = bestc[t]; best = sets[besti[t]]; }
+        if (bc == 0) break;   // nothing placeable (callers exclude wide supports)
+        L1Tile tile;
+        tile.local = best;
+        tile.qr = remap(pos, nL, best);
+        std::vector<int> rest;
+        for (int i : remain) {
+            if ((supports[i] & ~best) == 0) tile.ops.push_back(i);
+            else rest.push_back(i);
+        }
+        remain.swap(rest);
+        cur = best;
+        tiles.push_back(std::move(tile));
+    }
+    return tiles;
+}
+
+// ---------------------------------------------------------------------------
+// circuit plan: levels 2 and 3
+// ---------------------------------------------------------------------------
+
+static uint64_t phys_mask(uint64_t logical, const std::vector<int> &pos) {
+    uint64_t m = 0;
+    for (uint64_t t = logical; t; t &= t - 1) m |= bit(pos[__builtin_ctzll(t)]);
+    return m;
+}
+
+// Tile-local index of physical bits in S (sorted ascending).
+static uint32_t to_tile(uint64_t phys, uint64_t S) {
+    uint32_t out = 0;
+    int j = 0;
+    for (uint64_t s = S; s; s &= s - 1, ++j)
+        if (phys & (s & (~s + 1))) out |= 1u << j;
+    return out;
+}
+
+static int first_bit(uint64_t v) { return v ? __builtin_ctzll(v) : -1; }
+
+// Choose lane bits for a phase: six non-register tile bits, lowest first,
+// with pairwise distinct residues mod 6 where possible (so that the folded
+// LDS swizzle keeps the 64 lanes on distinct banks); lane b gets residue b
+// when all six residues are present.
+static void assign_lanes(int k, uint32_t regs, PhaseDesc &P) {
+    int lanes[6];
+    int nl = 0;
+    bool used_res[6] = {false, false, false, false, false, false};
+    uint32_t taken = regs;
+    for (int b = 0; b < k && nl < 6; ++b) {
+        if ((taken >> b) & 1) continue;
+        if (used_res[b % 6]) continue;
+        used_res[b % 6] = true;
+        lanes[nl++] = b;
+        taken |= 1u << b;
+    }
+    for (int b = 0; b < k && nl < 6; ++b) {   // fall back: any free bit
+        if ((taken >> b) & 1) continue;
+        lanes[nl++] = b;
+        taken |= 1u << b;
+    }
+    // order by residue so lane bit b has residue b where possible
+    std::stable_sort(lanes, lanes + nl, [](int a, int b) { return a % 6 < b % 6; });
+    for (int i = 0; i < 8; ++i) P.lane[i] = 0;
+    for (int i = 0; i < nl; ++i) P.lane[i] = (int8_t)lanes[i];
+    int nw = 0;
+    for (int i = 0; i < 8; ++i) P.wave[i] = 0;
+    for (int b = 0; b < k; ++b)
+        if (!((taken >> b) & 1)) P.wave[nw++] = (int8_t)b;
+}
+
+static void set_regs(uint32_t regs, int rb, PhaseDesc &P) {
+    int j = 0;
+    for (int i = 0; i < 8; ++i) P.reg[i] = 0;
+    for (uint32_t r = regs; r && j < rb; r &= r - 1) P.reg[j++] = (int8_t)__builtin_ctz(r);
+}
+
+struct L3Gate {
+    int gate;
+    int kind;
+    uint32_t t, mix, ctrl;
+    int diag;       // tile-local bit of the diagonal, -1
+    int tq0, tq1;   // tile-local bits of the gate's q[0], q[1] (-1 if absent)
+};
+
+static int op_type_of(int kind) {
+    switch (kind) {
+    case SVQ_Z: case SVQ_S: case SVQ_T: case SVQ_RZ: case SVQ_CZ: case SVQ_CPHASE:
+        return OP_DIAG;
+    case SVQ_X: case SVQ_CNOT:
+        return OP_XSWAP;
+    case SVQ_GIVENS:
+        return OP_GIVENS;
+    case SVQ_SWAP: case SVQ_U2:
+        return OP_MIX2;
+    default:
+        return OP_MIX1;
+    }
+}
+
+// Canonical load/store mapping: lanes are tile bits 0..5 (coalesced), the
+// registers are the highest RB tile bits.
+static uint32_t canonical_regs(int k, int rb) {
+    uint32_t r = 0;
+    for (int b = k - rb; b < k; ++b) r |= 1u << b;
+    return r;
+}
+
+static void plan_phases(int k, int rb, const std::vector<L3Gate> &gs, CircuitPlan &P) {
+    const uint32_t all = (k >= 32) ? ~0u : ((1u << k) - 1);
+    const uint32_t low6 = 63u;
+    (void)low6;
+    std::vector<int> remain(gs.size());
+    for (size_t i = 0; i < gs.size(); ++i) remain[i] = (int)i;
+    struct Ph { uint32_t regs; std::vector<int> ops; };
+    std::vector<Ph> phs;
+    while (!remain.empty()) {
+        // mapping: registers from the mixing qubits of the shallowest gates
+        uint64_t avail = all, regs = 0;
+        for (int i : remain) {
+            uint32_t M = gs[i].mix;
+            if ((M & ~avail) == 0 && popc(regs | M) <= rb) regs |= M;
+            else avail &= ~(uint64_t)gs[i].t;
+            if (!avail) break;
+        }
+        // fill with the highest tile bits outside the coalescing lanes first
+        for (int b = k - 1; b >= 6 && popc(regs) < rb; --b) regs |= 1u << b;
+        for (int b = k - 1; b >= 0 && popc(regs) < rb; --b) regs |= 1u << b;
+        // tile construction with dependency blocking on all targets
+        uint64_t av = all;
+        std::vector<int> G;
+        for (int i : remain) {
+            const L3Gate &g = gs[i];
+            if ((g.t & ~av) == 0 && (g.mix & ~regs) == 0) G.push_back(i);
+            else av &= ~(uint64_t)g.t;
+            if (!av) break;
+        }
+        std::vector<char> tk(gs.size(), 0);
+        for (int i : G) tk[i] = 1;
+        std::vector<int> rest;
+        for (int i : remain)
+            if (!tk[i]) rest.push_back(i);
+        remain.swap(rest);
+        if (!phs.empty() && phs.back().regs == (uint32_t)regs) {
+            phs.back().ops.insert(phs.back().ops.end(), G.begin(), G.end());
+        } else {
+            phs.push_back({(uint32_t)regs, G});
+        }
+    }
+    const uint32_t canon = canonical_regs(k, rb);
+    auto lanes_ok = [&](uint32_t regs) { return (regs & low6) == 0; };
+    if (phs.empty() || !lanes_ok(phs.front().regs)) phs.insert(phs.begin(), Ph{canon, {}});
+    if (!lanes_ok(phs.back().regs)) phs.push_back(Ph{canon, {}});
+    for (auto &ph : phs) {
+        PhaseDesc D;
+        std::memset(&D, 0, sizeof(D));
+        set_regs(ph.regs, rb, D);
+        if (lanes_ok(ph.regs)) {
+            // keep lanes on bits 0..5 (coalesced global access)
+            for (int i = 0; i < 6; ++i) D.lane[i] = (int8_t)i;
+            int nw = 0;
+            for (int b = 6; b < k; ++b)
+                if (!((ph.regs >> b) & 1)) D.wave[nw++] = (int8_t)b;
+        } else {
+            assign_lanes(k, ph.regs, D);
+        }
+        D.op0 = (int)P.ops.size();
+        D.nop = (int)ph.ops.size();
+        int regpos[32];
+        for (int i = 0; i < 32; ++i) regpos[i] = -1;
+        for (int j = 0; j < rb; ++j) regpos[(int)D.reg[j]] = j;
+        for (int i : ph.ops) {
+            const L3Gate &g = gs[i];
+            OpDesc o;
+            std::memset(&o, 0, sizeof(o));
+            o.gslot = -1;
+            o.type = op_type_of(g.kind);
+            o.cmask = g.ctrl;
+            o.pbit = g.diag;
+            o.b0 = o.b1 = 0;
+            if (o.type == OP_MIX1 || o.type == OP_XSWAP) {
+                o.b0 = regpos[g.kind == SVQ_CNOT ? g.tq1 : g.tq0];
+            } else if (o.type == OP_GIVENS || o.type == OP_MIX2) {
+                o.b0 = regpos[g.tq0];
+                o.b1 = regpos[g.tq1];
+            }
+            P.ops.push_back(o);
+            P.op_gate.push_back(g.gate);
+        }
+        P.phases.push_back(D);
+    }
+    P.n_phases_total += (int)phs.size();
+}
+
+std::string plan_circuit(int n, int g, const std::vector<GateN> &gates, svq_sched sched, int k,
+                         int rb, int c, const std::vector<int> &pos0, CircuitPlan &out) {
+    out = CircuitPlan();
+    out.n = n;
+    out.g = g;
+    const int nL = n - g;
+    const int keff = std::min(k, nL);
+    const int ceff = std::min(c, keff);
+    out.k = keff;
+    out.rb = rb;
+    out.c = ceff;
+    const int m = (int)gates.size();
+    std::vector<uint64_t> targets(m);
+    for (int i = 0; i < m; ++i) {
+        targets[i] = gates[i].tmask;
+        if (popc(targets[i]) > nL) return "gate wider than the local qubit count";
+    }
+    std::vector<int> pos = pos0;
+    out.pos_before = pos;
+    std::vector<L1Tile> tiles = (sched == SVQ_LAZY)
+                                    ? flat_tiling(n, nL, targets, pos)
+                                    : ad_hoc(n, nL, targets, depth_order(targets), pos);
+    out.pos_after = pos;
+    // replay layouts tile by tile for levels 2/3
+    std::vector<int> lay = pos0;
+    const uint64_t localpos = bit(nL) - 1;
+    const uint64_t forced = bit(ceff) - 1;
+    int qrtile = 0;
+    for (const L1Tile &T : tiles) {
+        if (!T.qr.empty()) {
+            Step s;
+            s.type = 0;
+            s.qr = T.qr;
+            out.steps.push_back(s);
+            out.n_qr += 1;
+            for (const Transposition &tr : T.qr) {
+                for (int q = 0; q < n; ++q) {
+                    if (lay[q] == tr.a) lay[q] = tr.b;
+                    else if (lay[q] == tr.b) lay[q] = tr.a;
+                }
+            }
+        }
+        // physical target masks for this tile
+        std::vector<uint64_t> pt(m, 0);
+        for (int i : T.ops) pt[i] = phys_mask(targets[i], lay);
+        std::vector<int> remain = T.ops;
+        while (!remain.empty()) {
+            uint64_t S = qubit_mapping(localpos, forced, remain, pt, keff);
+            std::vector<int> G = tile_construction(S, remain, pt);
+            if (G.empty()) return "internal: empty gate pass";
+            std::vector<char> tk(m, 0);
+            for (int i : G) tk[i] = 1;
+            std::vector<int> rest;
+            for (int i : remain)
+                if (!tk[i]) rest.push_back(i);
+            remain.swap(rest);
+            // level 3
+            std::vector<L3Gate> l3;
+            for (int i : G) {
+                const GateN &gt = gates[i];
+                L3Gate x;
+                x.gate = i;
+                x.kind = gt.kind;
+                x.tq0 = first_bit(to_tile(bit(lay[gt.q[0]]), S));
+                x.tq1 = gt.nq > 1 ? first_bit(to_tile(bit(lay[gt.q[1]]), S)) : -1;
+                x.t = to_tile(pt[i], S);
+                x.mix = to_tile(phys_mask(gt.mixmask, lay), S);
+                x.ctrl = to_tile(phys_mask(gt.ctrlmask, lay), S);
+                x.diag = gt.diag_q >= 0 ? first_bit(to_tile(bit(lay[gt.diag_q]), S)) : -1;
+                l3.push_back(x);
+            }
+            PassArgs pa;
+            std::memset(&pa, 0, sizeof(pa));
+            int j = 0;
+            for (uint64_t s = S; s; s &= s - 1) pa.tphys[j++] = (int8_t)__builtin_ctzll(s);
+            pa.phase0 = (int)out.phases.size();
+            plan_phases(keff, rb, l3, out);
+            pa.nphase = (int)out.phases.size() - pa.phase0;
+            pa.nblocks = 1 << (n - keff);
+            Step s;
+            s.type = 1;
+            s.idx = (int)out.passes.size();
+            out.steps.push_back(s);
+            for (int i : G) {
+                out.order.push_back(i);
+                out.pos_qrtile.push_back(qrtile);
+                out.pos_pass.push_back((int)out.passes.size());
+                out.pos_local.push_back(T.local);
+            }
+            out.passes.push_back(pa);
+        }
+        ++qrtile;
+    }
+    return "";
+}
+
+// ---------------------------------------------------------------------------
+// op coefficients
+// ---------------------------------------------------------------------------
+
+static void set_c(double *m, int idx, double re, double im) {
+    m[2 * idx] = re;
+    m[2 * idx + 1] = im;
+}
+
+void fill_ops(const std::vector<GateN> &gates, const double *theta, const std::vector<int> &op_gate,
+              std::vector<OpDesc> &ops, bool inverse) {
+    const double r2 = 1.0 / std::sqrt(2.0);
+    for (size_t i = 0; i < ops.size(); ++i) {
+        const GateN &g = gates[op_gate[i]];
+        OpDesc &o = ops[i];
+        const double t = g.param >= 0 ? theta[g.param] : g.angle;
+        const double c = std::cos(0.5 * t), s = std::sin(0.5 * t);
+        double *m = o.m;
+        std::memset(m, 0, sizeof(o.m));
+        std::memset(o.k, 0, sizeof(o.k));
+        o.gtype = GEN_NONE;
+        switch (g.kind) {
+        case SVQ_H: set_c(m, 0, r2, 0); set_c(m, 1, r2, 0); set_c(m, 2, r2, 0); set_c(m, 3, -r2, 0); break;
+        case SVQ_Y: set_c(m, 1, 0, -1); set_c(m, 2, 0, 1); break;
+        case SVQ_RX:
+            set_c(m, 0, c, 0); set_c(m, 1, 0, -s); set_c(m, 2, 0, -s); set_c(m, 3, c, 0);
+            o.gtype = GEN_MIX1; set_c(o.k, 1, 0.5, 0); set_c(o.k, 2, 0.5, 0);
+            break;
+        case SVQ_RY:
+            set_c(m, 0, c, 0); set_c(m, 1, -s, 0); set_c(m, 2, s, 0); set_c(m, 3, c, 0);
+            o.gtype = GEN_MIX1; set_c(o.k, 1, 0, -0.5); set_c(o.k, 2, 0, 0.5);
+            break;
+        case SVQ_U1:
+            for (int j = 0; j < 8; ++j) m[j] = g.mat[j];
+            break;
+        case SVQ_Z: set_c(m, 0, 1, 0); set_c(m, 1, -1, 0); break;
+        case SVQ_S: set_c(m, 0, 1, 0); set_c(m, 1, 0, 1); break;
+        case SVQ_T: set_c(m, 0, 1, 0); set_c(m, 1, r2, r2); break;
+        case SVQ_RZ:
+            set_c(m, 0, std::cos(0.5 * t), -std::sin(0.5 * t));
+            set_c(m, 1, std::cos(0.5 * t), std::sin(0.5 * t));
+            o.gtype = GEN_DIAG; o.k[0] = 0.5; o.k[1] = -0.5;
+            break;
+        case SVQ_CZ: set_c(m, 0, 1, 0); set_c(m, 1, -1, 0); break;
+        case SVQ_CPHASE:
+            set_c(m, 0, 1, 0); set_c(m, 1, std::cos(t), std::sin(t));
+            o.gtype = GEN_DIAG; o.k[0] = 0.0; o.k[1] = -1.0;
+            break;
+        case SVQ_GIVENS:
+            m[0] = c; m[1] = s;
+            o.gtype = GEN_GIVENS;
+            break;
+        case SVQ_SWAP:
+            set_c(m, 0, 1, 0); set_c(m, 1 * 4 + 2, 1, 0); set_c(m, 2 * 4 + 1, 1, 0); set_c(m, 15, 1, 0);
+            break;
+        case SVQ_U2:
+            for (int j = 0; j < 32; ++j) m[j] = g.mat[j];
+            break;
+        default:   // X, CNOT: pure swap
+            break;
+        }
+        if (!inverse) continue;
+        // U^dagger
+        if (o.type == OP_DIAG) {
+            m[1] = -m[1];
+            m[3] = -m[3];
+        } else if (o.type == OP_GIVENS) {
+            m[1] = -m[1];
+        } else if (o.type == OP_MIX1 || o.type == OP_MIX2) {
+            const int d = o.type == OP_MIX1 ? 2 : 4;
+            double tmp[32];
+            for (int r = 0; r < d; ++r)
+                for (int cc = 0; cc < d; ++cc) {
+                    tmp[2 * (r * d + cc)] = m[2 * (cc * d + r)];
+                    tmp[2 * (r * d + cc) + 1] = -m[2 * (cc * d + r) + 1];
+                }
+            std::memcpy(m, tmp, sizeof(double) * 2 * d * d);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pauli plan
+// ---------------------------------------------------------------------------
+
+static uint32_t pext32(uint32_t v, const int8_t *bits, int nb) {
+    uint32_t out = 0;
+    for (int i = 0; i < nb; ++i)
+        if ((v >> bits[i]) & 1) out |= 1u << i;
+    return out;
+}
+
+std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched sched, int k,
+                        int c, int tpb_log2, const std::vector<int> &pos0, PauliPlan &out) {
+    out = PauliPlan();
+    out.n = n;
+    out.g = g;
+    const int nL = n - g;
+    const int keff = std::min(k, nL);
+    const int ceff = std::min(c, keff);
+    out.k = keff;
+    out.c = ceff;
+    const uint64_t full = n >= 64 ? ~0ULL : (bit(n) - 1);
+    // group by flip mask, first appearance order
+    std::unordered_map<uint64_t, int> gid;
+    out.group_of_term.resize(nt);
+    for (int t = 0; t < nt; ++t) {
+        if ((terms[t].x & ~full) || (terms[t].z & ~full)) return "pauli mask beyond n qubits";
+        if (!std::isfinite(terms[t].coef)) return "non-finite coefficient";
+        auto it = gid.find(terms[t].x);
+        int id;
+        if (it == gid.end()) {
+            id = (int)out.group_x.size();
+            gid[terms[t].x] = id;
+            out.group_x.push_back(terms[t].x);
+            out.group_terms.emplace_back();
+        } else {
+            id = it->second;
+        }
+        out.group_of_term[t] = id;
+        out.group_terms[id].push_back(t);
+    }
+    const int ng = (int)out.group_x.size();
+    // level 1 over groups (lazy) or terms in index order (eager)
+    std::vector<int> pos = pos0;
+    out.pos_before = pos;
+    std::vector<char> wide(ng, 0);
+    for (int i = 0; i < ng; ++i)
+        if (popc(out.group_x[i]) > nL) wide[i] = 1;
+    struct GTile { uint64_t local; std::vector<int> groups; std::vector<Transposition> qr; };
+    std::vector<GTile> gtiles;
+    if (sched == SVQ_LAZY) {
+        std::vector<uint64_t> sup;
+        std::vector<int> w, ids;
+        for (int i = 0; i < ng; ++i) {
+            if (wide[i]) continue;
+            sup.push_back(out.group_x[i]);
+            w.push_back((int)out.group_terms[i].size());
+            ids.push_back(i);
+        }
+        std::vector<L1Tile> t1 = tiling_pauli(n, nL, sup, w, pos);
+        for (auto &t : t1) {
+            GTile gt;
+            gt.local = t.local;
+            gt.qr = t.qr;
+            for (int i : t.ops) gt.groups.push_back(ids[i]);
+            gtiles.push_back(std::move(gt));
+        }
+    } else {
+        std::vector<uint64_t> tg;
+        std::vector<int> ord;
+        std::vector<int> term_ids;
+        for (int t = 0; t < nt; ++t) {
+            if (wide[out.group_of_term[t]]) continue;
+            tg.push_back(terms[t].x);
+            ord.push_back((int)ord.size());
+            term_ids.push_back(t);
+        }
+        std::vector<L1Tile> t1 = ad_hoc(n, nL, tg, ord, pos);
+        for (auto &t : t1) {
+            GTile gt;
+            gt.local = t.local;
+            gt.qr = t.qr;
+            std::vector<char> seen(ng, 0);
+            for (int i : t.ops) {
+                int gi = out.group_of_term[term_ids[i]];
+                if (!seen[gi]) {
+                    seen[gi] = 1;
+                    gt.groups.push_back(gi);
+                }
+            }
+            gtiles.push_back(std::move(gt));
+        }
+    }
+    out.pos_after = pos;
+    for (int i = 0; i < ng; ++i)
+        if (wide[i]) out.wide_groups.push_back(i);
+    // For eager, a group may appear in several QR tiles (its terms were split
+    // by intervening reorders); it is evaluated once, in its first tile.
+    std::vector<char> done(ng, 0);
+
+    (void)tpb_log2;
+    const int TPB = evc_tpb(keff);     // EVC threads per tile (log2)
+    const int Q = keff - 1 - TPB;      // EVC cube bits (half space)
+    const int TPBH = hpsi_tpb(keff);   // H|psi> threads per tile (log2)
+    const int QH = keff - TPBH;        // H|psi> cube bits (full space)
+    if (keff < 8) return "tile too small for the Pauli pass";
+    std::vector<int> lay = pos0;
+    const uint64_t forced = bit(ceff) - 1;
+    const uint64_t localpos = bit(nL) - 1;
+    int qrtile = 0;
+    for (const GTile &T : gtiles) {
+        if (!T.qr.empty()) {
+            Step s;
+            s.type = 0;
+            s.qr = T.qr;
+            out.steps.push_back(s);
+            out.n_qr += 1;
+            for (const Transposition &tr : T.qr)
+                for (int q = 0; q < n; ++q) {
+                    if (lay[q] == tr.a) lay[q] = tr.b;
+                    else if (lay[q] == tr.b) lay[q] = tr.a;
+                }
+        }
+        // physical flip masks of this tile's groups
+        std::vector<int> rem;
+        std::vector<uint64_t> px(ng, 0);
+        for (int gi : T.groups) {
+            if (done[gi]) continue;
+            done[gi] = 1;
+            px[gi] = phys_mask(out.group_x[gi], lay);
+            if (popc(px[gi] & ~forced) > keff - ceff) {
+                out.wide_groups.push_back(gi);   // fits no tile: direct kernel
+                continue;
+            }
+            rem.push_back(gi);
+        }
+        // level 2: greedy cover of flip masks by k-bit tiles containing the
+        // forced low bits
+        while (!rem.empty()) {
+            uint64_t S = forced;
+            std::vector<char> in(ng, 0);
+            while (true) {
+                int best = -1, bneed = 99;
+                size_t bw = 0;
+                for (int gi : rem) {
+                    if (in[gi]) continue;
+                    int need = popc(px[gi] & ~S);
+                    if (popc(S) + need > keff) continue;
+                    size_t w = out.group_terms[gi].size();
+                    if (need < bneed || (need == bneed && w > bw)) {
+                        best = gi;
+                        bneed = need;
+                        bw = w;
+                    }
+                }
+                if (best < 0) break;
+                S |= px[best];
+                for (int gi : rem)
+                    if (!in[gi] && (px[gi] & ~S) == 0) in[gi] = 1;
+            }
+            // fill up with the most used free local bits of the remaining groups
+            while (popc(S) < keff) {
+                int cnt[64] = {0};
+                for (int gi : rem)
+                    if (!in[gi])
+                        for (uint64_t v = px[gi] & ~S; v; v &= v - 1) cnt[__builtin_ctzll(v)]++;
+                int bb = -1, bc = -1;
+                for (int b = 0; b < nL; ++b)
+                    if (!((S >> b) & 1) && ((localpos >> b) & 1) && cnt[b] > bc) {
+                        bc = cnt[b];
+                        bb = b;
+                    }
+                if (bb < 0) break;
+                S |= bit(bb);
+            }
+            for (int gi : rem)
+                if (!in[gi] && (px[gi] & ~S) == 0) in[gi] = 1;
+            std::vector<int> pg, rest;
+            for (int gi : rem) (in[gi] ? pg : rest).push_back(gi);
+            rem.swap(rest);
+            // ---- emit EVC pass
+            EvcPassArgs ea;
+            std::memset(&ea, 0, sizeof(ea));
+            int8_t tph[16];
+            {
+                int j = 0;
+                for (uint64_t s = S; s; s &= s - 1) tph[j++] = (int8_t)__builtin_ctzll(s);
+            }
+            std::memcpy(ea.tphys, tph, 16);
+            ea.group0 = (int)out.groups.size();
+            ea.ngroups = (int)pg.size();
+            ea.nblocks = 1 << (n - keff);
+            ea.part0 = out.total_blocks;
+            out.total_blocks += ea.nblocks;
+            // ---- emit H|psi> pass (fixed cube: top QH tile bits)
+            HpsiPassArgs ha;
+            std::memset(&ha, 0, sizeof(ha));
+            std::memcpy(ha.tphys, tph, 16);
+            for (int j = 0; j < TPBH; ++j) ha.tbits[j] = (int8_t)j;
+            for (int j = 0; j < QH; ++j) ha.wbits[j] = (int8_t)(TPBH + j);
+            ha.group0 = (int)out.hgroups.size();
+            ha.ngroups = (int)pg.size();
+            ha.accumulate = out.hpasses.empty() ? 0 : 1;
+            const uint32_t htmask = (1u << TPBH) - 1;
+            for (int gi : pg) {
+                const uint32_t xl = to_tile(px[gi], S);
+                EvcGroup G;
+                std::memset(&G, 0, sizeof(G));
+                G.xl = xl;
+                G.hbit = xl ? 31 - __builtin_clz(xl) : keff - 1;
+                int nb = 0;
+                for (int b = 0; b < keff; ++b) {
+                    if (b == G.hbit) continue;
+                    if (nb < TPB) G.tbits[nb] = (int8_t)b;
+                    else G.wbits[nb - TPB] = (int8_t)b;
+                    ++nb;
+                }
+                uint32_t tmask = 0;
+                for (int j = 0; j < TPB; ++j) tmask |= 1u << G.tbits[j];
+                G.t0 = (int)out.terms.size();
+                G.nt = (int)out.group_terms[gi].size();
+                HpsiGroup HG;
+                std::memset(&HG, 0, sizeof(HG));
+                HG.xl = xl;
+                HG.xt = xl & htmask;
+                HG.xw = xl >> TPBH;
+                HG.t0 = (int)out.hterms.size();
+                HG.nt = G.nt;
+                for (int t : out.group_terms[gi]) {
+                    const uint64_t pz = phys_mask(terms[t].z, lay);
+                    const uint32_t zl = to_tile(pz, S);
+                    const uint64_t zg = pz & ~S;
+                    const int nY = popc(terms[t].x & terms[t].z);
+                    EvcTerm et;
+                    std::memset(&et, 0, sizeof(et));
+                    if (xl) {
+                        // pair (j, j^x) over j with bit h clear:
+                        // nY even: 2 (-1)^{nY/2} s_j Re w ; nY odd: 2 (-1)^{(nY+1)/2} s_j Im w
+                        if ((nY & 1) == 0) {
+                            et.coef = 2.0 * terms[t].coef * (((nY / 2) & 1) ? -1.0 : 1.0);
+                            et.use_im = 0;
+                        } else {
+                            et.coef = 2.0 * terms[t].coef * ((((nY + 1) / 2) & 1) ? -1.0 : 1.0);
+                            et.use_im = 1;
+                        }
+                    } else {
+                        et.coef = terms[t].coef;
+                        et.use_im = (zl >> G.hbit) & 1;   // difference array
+                    }
+                    const uint32_t zr = zl & ~(1u << G.hbit);
+                    et.zg = zg;
+                    et.zt = zr & tmask;
+                    et.zw = pext32(zr, G.wbits, Q);
+                    G.need |= et.use_im ? 2 : 1;
+                    out.terms.push_back(et);
+                    HpsiTerm ht;
+                    std::memset(&ht, 0, sizeof(ht));
+                    const double a = terms[t].coef;
+                    switch (nY & 3) {
+                    case 0: ht.are = a; ht.aim = 0; break;
+                    case 1: ht.are = 0; ht.aim = a; break;
+                    case 2: ht.are = -a; ht.aim = 0; break;
+                    default: ht.are = 0; ht.aim = -a; break;
+                    }
+                    ht.zg = zg;
+                    ht.zt = zl & htmask;
+                    ht.zw = zl >> TPBH;
+                    out.hterms.push_back(ht);
+                }
+                out.groups.push_back(G);
+                out.hgroups.push_back(HG);
+                out.order.push_back(gi);
+                out.pos_qrtile.push_back(qrtile);
+                out.pos_pass.push_back((int)out.passes.size());
+                out.pos_local.push_back(T.local);
+            }
+            Step s;
+            s.type = 1;
+            s.idx = (int)out.passes.size();
+            out.steps.push_back(s);
+            out.passes.push_back(ea);
+            out.hpasses.push_back(ha);
+        }
+        ++qrtile;
+    }
+    return "";
+}
+
+}  // namespace svq

@@ -1,0 +1,129 @@
+// Descriptor tables shared by the host planner and the HIP kernels.
+//
+// A plan is a sequence of steps.  A QR step permutes physical bit positions
+// (an involution: disjoint transpositions).  A gate pass streams the state
+// once: every workgroup owns one tile of 2^k amplitudes whose indices agree
+// on all non-tile bits (all tile bits are chunk-local, so a tile never spans
+// two chunks -- narrow access, constraint C2), keeps it in registers and LDS,
+// and applies a run of gates.  Inside a pass the tile is walked in register
+// phases: in a phase every thread holds 2^RB amplitudes that differ in the
+// phase's RB "register" tile bits; gates that mix amplitudes act only on
+// register bits, diagonal gates and controls act on any tile bit.  Between
+// phases the tile is transposed through LDS.
+#pragma once
+#include <cstdint>
+
+namespace svq {
+
+constexpr int kMaxTileBits = 14;
+constexpr int kLaneBits = 6;      // wave64
+
+// Register bits per thread of a gate pass over 2^k amplitudes (at least one
+// wave per tile).
+constexpr int gate_rb(int k) { return k - 6 < 4 ? k - 6 : 4; }
+// Threads (log2) of a Pauli pass: every thread owns a 2^(k-1-tpb) cube of
+// the half space (EVC) or a 2^(k-tpb) cube of outputs (H|psi>).
+constexpr int evc_tpb(int k) { return k - 5 > 6 ? k - 5 : 6; }
+constexpr int hpsi_tpb(int k) { return k - 4 > 6 ? k - 4 : 6; }
+
+// Gate-pass operations.  b0/b1 are register-bit positions of the mixing
+// qubits (b0 = the gate matrix's local bit 0), pbit a tile-local bit, cmask
+// tile-local control bits that must all be 1.
+enum OpType : int32_t {
+    OP_DIAG = 0,    // amp *= (bit pbit ? d1 : d0);        m = {d0.re, d0.im, d1.re, d1.im}
+    OP_MIX1 = 1,    // 2x2 dense on register bit b0;        m = row-major complex 2x2
+    OP_XSWAP = 2,   // swap along register bit b0 (X / CNOT)
+    OP_GIVENS = 3,  // real rotation of (|b0=1,b1=0>, |b0=0,b1=1>); m = {c, s}
+    OP_MIX2 = 4,    // 4x4 dense on register bits (b0, b1);  m = row-major complex 4x4
+};
+
+// Generator K of a parametric op (U = exp(-i t K)), for the adjoint sweep.
+enum GenType : int32_t {
+    GEN_NONE = 0,
+    GEN_DIAG = 1,    // diagonal on pbit with control cmask: k = {k0, k1} (real)
+    GEN_MIX1 = 2,    // 2x2 Hermitian on b0: k = row-major complex 2x2
+    GEN_GIVENS = 3,  // (X_b0 Y_b1 - Y_b0 X_b1)/4
+};
+
+struct OpDesc {
+    int32_t type;
+    int32_t b0, b1;
+    int32_t pbit;
+    uint32_t cmask;
+    int32_t gslot;   // adjoint: slot of this gate in the gradient partials (-1: none)
+    int32_t gtype;   // GenType
+    int32_t pad;
+    double m[32];
+    double k[8];
+};
+
+struct PhaseDesc {
+    int8_t reg[8];    // tile-local bit of register bit b
+    int8_t lane[8];   // tile-local bit of lane bit b (6 used)
+    int8_t wave[8];   // tile-local bit of wave bit b
+    int32_t op0, nop;
+};
+
+struct PassArgs {
+    int32_t nphase;
+    int32_t phase0;
+    int32_t gslot_base;   // adjoint partial-buffer offset of this pass
+    int32_t nblocks;
+    int8_t tphys[16];     // physical bit of tile-local bit j (ascending)
+};
+
+// Read-only Pauli pass (EVC) and H|psi> pass.
+struct EvcGroup {
+    uint32_t xl;          // tile-local flip mask (0 for the diagonal group)
+    int32_t hbit;         // tile-local half-space bit (the pair partner flips it)
+    int32_t t0, nt;       // term range
+    int8_t tbits[16];     // tile-local bits of the thread index (low to high)
+    int8_t wbits[8];      // tile-local bits of the per-thread cube index
+    int32_t need;         // bit0: real array used, bit1: imaginary array used
+    int32_t pad;
+};
+
+struct EvcTerm {
+    double coef;          // a_t with the i^{nY} sign and pair factor folded in
+    uint64_t zg;          // physical z bits outside the tile (per-tile sign)
+    uint32_t zt;          // tile-local z bits on thread-index bits
+    uint32_t zw;          // z bits in cube-index coordinates (Walsh index)
+    int32_t use_im;       // 1: imaginary (or difference) array
+    int32_t pad;
+};
+
+struct EvcPassArgs {
+    int32_t ngroups;
+    int32_t group0;
+    int32_t part0;        // offset of this pass's block partials
+    int32_t nblocks;
+    int8_t tphys[16];
+};
+
+// H|psi> pass: fixed output cube for the whole pass.
+struct HpsiGroup {
+    uint32_t xl;          // tile-local flip mask
+    uint32_t xt;          // flip bits on thread-index bits
+    uint32_t xw;          // flip bits in cube coordinates
+    int32_t t0, nt;
+    int32_t pad;
+};
+
+struct HpsiTerm {
+    double are, aim;      // a_t * i^{nY}
+    uint64_t zg;
+    uint32_t zt;
+    uint32_t zw;
+};
+
+struct HpsiPassArgs {
+    int32_t ngroups;
+    int32_t group0;
+    int32_t accumulate;   // 0: first pass writes lambda, 1: lambda += pass
+    int32_t pad;
+    int8_t tphys[16];
+    int8_t tbits[16];     // thread-index bits (tile-local)
+    int8_t wbits[8];      // cube bits (tile-local)
+};
+
+}  // namespace svq

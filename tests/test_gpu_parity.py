@@ -1,0 +1,144 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    import paper_2410_04252_amd as P
+    torch.cuda.set_device(0)
+    return P
+
+
+def _tol_energy(e_ref, ham, rel):
+    return rel * max(abs(e_ref), 1e-3 * float(np.abs(ham.coef).sum()))
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,g", [(12, 2), (14, 3), (17, 4)])
+def test_qr_permute_bitexact(P, n, g, dtype):
+    import torch
+    _print(f"qr_permute n={n} g={g} {dtype}")
+    rng = np.random.default_rng(n * 7 + g)
+    v = W.random_state(n, 5 + n, np.complex64 if dtype == "c64" else np.complex128)
+    buf = torch.empty(1 << n, dtype=torch.complex64 if dtype == "c64" else torch.complex128,
+                      device="cuda")
+    st = P.State(n, g, dtype, buf=buf)
+    st.set_amplitudes(v)
+    pos = list(range(n))
+    for trial in range(4):
+        if trial % 2 == 0:   # a QR: disjoint local/global transpositions
+            s = int(rng.integers(1, g + 1))
+            loc = rng.choice(n - g, size=s, replace=False)
+            glo = rng.choice(np.arange(n - g, n), size=s, replace=False)
+            phys_new = list(range(n))
+            for a, b in zip(loc, glo):
+                phys_new[a], phys_new[b] = phys_new[b], phys_new[a]
+            new = [phys_new[p] for p in pos]
+        else:                # an arbitrary relayout (two passes)
+            new = list(rng.permutation(n))
+        before = buf.cpu().numpy().copy()
+        st.qr_permute(new)
+        torch.cuda.synchronize()
+        after = buf.cpu().numpy()
+        want = oracle.qr_permute(before, pos, new)
+        assert np.array_equal(after, want), f"trial {trial}"
+        assert st.layout() == [int(x) for x in new]
+        pos = [int(x) for x in new]
+    np.testing.assert_array_equal(st.get_amplitudes(), v)
+    st.close()
+
+
+CIRCS = {
+    "hea12": lambda: (W.hea(12, 4, 4253), 2),
+    "fabric16": lambda: (W.fabric(16, 8, 11), 3),
+    "random14": lambda: (W.random_circuit(14, 120, 12), 3),
+}
+
+
+@pytest.mark.parametrize("sched", [0, 1])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("name", list(CIRCS))
+@pytest.mark.parametrize("k", [8, 10, 12])
+def test_circuit_parity(P, name, dtype, sched, k):
+    circ, g = CIRCS[name]()
+    n = circ.n
+    if k > n - g:
+        pytest.skip("tile wider than the local qubits")
+    _print(f"circuit {name} {dtype} sched={sched} k={k}")
+    ref = oracle.run_circuit(circ)
+    st = P.State(n, g, dtype)
+    st.set_basis(circ.psi0_index)
+    stats = st.apply(circ, sched=sched, tile_k=k)
+    got = st.get_amplitudes()
+    tol = 1e-5 if dtype == "c64" else 1e-12
+    assert np.max(np.abs(got - ref)) < tol
+    assert stats.n_gate_passes >= 1
+    st.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_circuit_random_state_input(P, dtype):
+    n, g = 15, 3
+    circ = W.fabric(n, 6, 21)
+    v = W.random_state(n, 22)
+    ref = oracle.apply_circuit(v, circ.gates, circ.theta)
+    st = P.State(n, g, dtype)
+    st.set_amplitudes(v)
+    st.apply(circ)
+    got = st.get_amplitudes()
+    assert np.max(np.abs(got - ref)) < (1e-5 if dtype == "c64" else 1e-12)
+    st.close()
+
+
+HAMS = {
+    "rand12": lambda: (12, 2, W.random_pauli(12, 64, 4253 + 1000)),
+    "jw16": lambda: (16, 3, W.jw_terms(16, 300, 31)),
+    "jw18": lambda: (18, 4, W.jw_terms(18, 500, 32)),
+}
+
+
+@pytest.mark.parametrize("sched", [0, 1])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("name", list(HAMS))
+def test_expectation_parity(P, name, dtype, sched):
+    n, g, ham = HAMS[name]()
+    _print(f"expectation {name} {dtype} sched={sched}")
+    v = W.random_state(n, 40 + n)
+    e_ref = oracle.expectation(v, ham)
+    st = P.State(n, g, dtype)
+    st.set_amplitudes(v)
+    e, stats = st.expectation(ham, sched=sched)
+    rel = 1e-6 if dtype == "c64" else 1e-12
+    assert abs(e - e_ref) <= _tol_energy(e_ref, ham, rel), (e, e_ref)
+    # the logical state is unchanged by the reorders
+    got = st.get_amplitudes()
+    assert np.max(np.abs(got - v.astype(got.dtype))) == 0
+    st.close()
+
+
+def test_grad_parity_small(P):
+    n, g = 12, 2
+    circ = W.fabric(n, 4, 51)
+    ham = W.jw_terms(n, 80, 52)
+    e_ref, g_ref = oracle.adjoint_grad(circ, ham)
+    for dtype, rel in (("c64", 1e-5), ("c128", 1e-11)):
+        _print(f"grad {dtype}")
+        st = P.State(n, g, dtype)
+        st.set_basis(circ.psi0_index)
+        e, grad, _ = st.grad(circ, ham)
+        assert abs(e - e_ref) <= _tol_energy(e_ref, ham, 1e-6 if dtype == "c64" else 1e-12)
+        assert np.linalg.norm(grad - g_ref) <= rel * np.linalg.norm(g_ref)
+        st.close()
