@@ -1,0 +1,323 @@
+"""Benchmark of the state-vector hot path on one MI355X.
+
+One step = one VQE energy evaluation of the 30-qubit fabric-style workload
+(complex64, g = 5 emulated global qubits, 16 brick layers = 336 gates, 2000
+Jordan-Wigner-like Pauli strings): prepare psi0, QSU under the lazy-QR
+schedule, EVC under the lazy-QR schedule.  Inputs are synthetic and seeded
+(workloads.config("fabric30")); the state lives in HBM for the whole run.
+
+Printed: one JSON line.  ``value`` is QSU gates/s (gates per second of the QSU
+part of the timed steps, measured with HIP events on the library's stream);
+the EVC terms/s, the adjoint-vs-parameter-shift gradient rates (24-qubit
+400-parameter workload), lazy/eager QR counts, the roofline of the gate pass
+and the CPU-oracle baseline are extra keys of the same line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QSU gates/s + HBM GB/s frac at 30q; EVC terms/s; adjoint vs param-shift grad/s"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gate_pass_fabric30.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "svq_dev.hpp", "plan.cpp"):
+        with open(os.path.join(ROOT, "paper_2410_04252_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measure_main(P, W, torch, args):
+    cfg = W.config(args.workload)
+    circ, ham, g = cfg["circuit"], cfg["ham"], cfg["g"]
+    n = circ.n
+    dtype = args.dtype or cfg["dtype"]
+    esz = 8 if dtype == "c64" else 16
+    S = (1 << n) * esz
+    st = P.State(n, g, dtype)
+    h = st.h
+    gates_c = P.gates_array(circ.gates)
+    terms_c = P.paulis_array(ham)
+    m, nt = len(circ.gates), len(ham.coef)
+    theta = circ.theta
+    e_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(prof_events=None):
+        P.sv_set_basis(h, circ.psi0_index)
+        if prof_events:
+            prof_events[0].record(stream)
+        s1 = P.sv_apply_circuit(h, gates_c, m, theta, len(theta), P.LAZY, args.tile_k)
+        if prof_events:
+            prof_events[1].record(stream)
+        _, s2 = P.sv_expectation(h, terms_c, nt, P.LAZY, energy_dev=e_dev.data_ptr(),
+                                 want_host=False)
+        if prof_events:
+            prof_events[2].record(stream)
+        return s1, s2
+
+    log(f"[bench] workload {args.workload}: n={n} g={g} {dtype} gates={m} terms={nt}")
+    t0 = time.time()
+    s1, s2 = step()          # plans are built (and cached) here
+    torch.cuda.synchronize()
+    log(f"[bench] first step (incl. planning {s1.ms_plan:.1f} + {s2.ms_plan:.1f} ms): "
+        f"{time.time() - t0:.2f} s")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    P.sv_profile(h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    qsu_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    evc_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    n_gp, t_gp = P.sv_profile_read(h, P.PROF_GATE)
+    n_qr, t_qr = P.sv_profile_read(h, P.PROF_QR)
+    n_ev, t_ev = P.sv_profile_read(h, P.PROF_EVC)
+    P.sv_profile(h, 0)
+    energy = float(e_dev.item())
+    log(f"[bench] step {ms_step:.2f} ms: QSU {qsu_ms:.2f} ms ({s1.n_gate_passes} passes, "
+        f"{s1.n_qr} QR), EVC {evc_ms:.2f} ms ({s2.n_evc_passes} passes, {s2.n_qr} QR), E={energy:.8f}")
+    gp_avg_ms = t_gp / max(1, n_gp)
+    gp_bytes = 2.0 * S                     # one read + one write of the state per launch
+    achieved = gp_bytes / (gp_avg_ms * 1e-3) / 1e9
+    # eager comparison (one run, not part of the timed steps)
+    P.sv_set_basis(h, circ.psi0_index)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    se = P.sv_apply_circuit(h, gates_c, m, theta, len(theta), P.EAGER, args.tile_k)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    eager_first_ms = (tb - ta) * 1e3
+    P.sv_set_basis(h, circ.psi0_index)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    se = P.sv_apply_circuit(h, gates_c, m, theta, len(theta), P.EAGER, args.tile_k)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - ta) * 1e3
+    _, se2 = P.sv_expectation(h, terms_c, nt, P.EAGER)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    P.sv_set_basis(h, circ.psi0_index)
+    P.sv_apply_circuit(h, gates_c, m, theta, len(theta), P.LAZY, args.tile_k)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    _, se2 = P.sv_expectation(h, terms_c, nt, P.EAGER)
+    torch.cuda.synchronize()
+    evc_eager_ms = (time.perf_counter() - ta) * 1e3
+    log(f"[bench] eager QSU {eager_ms:.2f} ms ({se.n_qr} QR, {se.n_gate_passes} passes); "
+        f"eager EVC {evc_eager_ms:.2f} ms ({se2.n_qr} QR)")
+    st.close()
+    out = dict(
+        n=n, g=g, dtype=dtype, m=m, nt=nt, S=S, ms_step=ms_step, qsu_ms=qsu_ms, evc_ms=evc_ms,
+        energy=energy,
+        qsu=dict(gates_per_s=m / (qsu_ms * 1e-3), ms=qsu_ms, gate_passes=s1.n_gate_passes,
+                 qr_lazy=s1.n_qr, qr_eager=se.n_qr, eager_ms=eager_ms,
+                 eager_gate_passes=se.n_gate_passes, plan_ms=s1.ms_plan,
+                 algorithmic_gbs=s1.bytes / (qsu_ms * 1e-3) / 1e9,
+                 hbm_frac=s1.bytes / (qsu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 gate_pass_avg_ms=gp_avg_ms, qr_pass_avg_ms=t_qr / max(1, n_qr)),
+        evc=dict(terms_per_s=nt / (evc_ms * 1e-3), ms=evc_ms, evc_passes=s2.n_evc_passes,
+                 groups=s2.n_groups, qr_lazy=s2.n_qr, qr_eager=se2.n_qr, eager_ms=evc_eager_ms,
+                 evc_pass_avg_ms=t_ev / max(1, n_ev), plan_ms=s2.ms_plan,
+                 read_gbs=s2.n_evc_passes * S / (max(1e-9, t_ev / max(1, args.steps)) * 1e-3) / 1e9),
+        roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                      kernel="k_gate_pass<float,%d,4,false>" % (s1.tile_k or 12),
+                      bytes_per_launch=gp_bytes, launches=n_gp, avg_ms=gp_avg_ms),
+    )
+    return out
+
+
+def measure_grad(P, W, torch, args):
+    cfg = W.config("grad24")
+    circ, ham = cfg["circuit"], cfg["ham"]
+    n = circ.n
+    g = 5
+    st = P.State(n, g, "c64")
+    h = st.h
+    gates_c = P.gates_array(circ.gates)
+    terms_c = P.paulis_array(ham)
+    m, nt, npar = len(circ.gates), len(ham.coef), len(circ.theta)
+    theta = circ.theta.copy()
+    log(f"[bench] gradient workload grad24: n={n} params={npar} gates={m} terms={nt}")
+    # adjoint
+    P.sv_set_basis(h, circ.psi0_index)
+    P.sv_grad(h, gates_c, m, theta, npar, terms_c, nt, P.LAZY)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.sv_set_basis(h, circ.psi0_index)
+        e_adj, g_adj, sg = P.sv_grad(h, gates_c, m, theta, npar, terms_c, nt, P.LAZY)
+    torch.cuda.synchronize()
+    adj_ms = (time.perf_counter() - t0) * 1e3 / reps
+    # parameter shift on the GPU (exact rules: 2 evaluations for CPHASE, 4 for GIVENS)
+    r2 = math.sqrt(2.0)
+    rules = {"CPHASE": ((math.pi / 2, 0.5),),
+             "GIVENS": ((math.pi / 2, (r2 + 1) / (4 * r2)), (3 * math.pi / 2, -(r2 - 1) / (4 * r2)))}
+    kind_of = {}
+    for kind, qs, p in circ.gates:
+        kind_of[p] = kind
+    evals = []
+    for p in range(npar):
+        for shift, w in rules[kind_of[p]]:
+            evals.append((p, +shift, w))
+            evals.append((p, -shift, -w))
+    e_dev = torch.zeros(len(evals), dtype=torch.float64, device="cuda")
+    base = e_dev.data_ptr()
+
+    def run_shift(limit=None):
+        th = theta.copy()
+        for i, (p, s, _) in enumerate(evals[:limit]):
+            th[p] = theta[p] + s
+            P.sv_set_basis(h, circ.psi0_index)
+            P.sv_apply_circuit(h, gates_c, m, th, npar, P.LAZY, 0)
+            P.sv_expectation(h, terms_c, nt, P.LAZY, energy_dev=base + 8 * i, want_host=False)
+            th[p] = theta[p]
+
+    run_shift(8)   # warm plans
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_shift()
+    torch.cuda.synchronize()
+    ps_ms = (time.perf_counter() - t0) * 1e3
+    ev = e_dev.cpu().numpy()
+    g_ps = [0.0] * npar
+    for (p, s, w), e in zip(evals, ev):
+        g_ps[p] += w * e
+    import numpy as np
+    g_ps = np.array(g_ps)
+    rel = float(np.linalg.norm(g_adj - g_ps) / max(1e-300, np.linalg.norm(g_ps)))
+    st.close()
+    log(f"[bench] adjoint {adj_ms:.2f} ms/grad; param-shift {ps_ms:.1f} ms/grad "
+        f"({len(evals)} evaluations); rel diff {rel:.2e}")
+    return dict(workload="grad24", n=n, params=npar, terms=nt, adjoint_ms=adj_ms,
+                adjoint_grad_per_s=1e3 / adj_ms, param_shift_ms=ps_ms,
+                param_shift_grad_per_s=1e3 / ps_ms, param_shift_evaluations=len(evals),
+                speedup=ps_ms / adj_ms, rel_diff_adjoint_vs_shift=rel)
+
+
+def measure_cpu(W, main, budget_s):
+    import numpy as np
+    import oracle
+    cfg = W.config(main["workload"])
+    circ, ham = cfg["circuit"], cfg["ham"]
+    n = circ.n
+    log(f"[bench] cpu baseline: oracle on {oracle.threads()} threads, n={n} complex128")
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[circ.psi0_index] = 1.0
+    done, t_q = 0, 0.0
+    while done < len(circ.gates) and t_q < budget_s * 0.6:
+        t0 = time.perf_counter()
+        oracle.apply_circuit_inplace(psi, circ.gates[done:done + 1], circ.theta)
+        t_q += time.perf_counter() - t0
+        done += 1
+    terms_done, t_e = 0, 0.0
+    while terms_done < len(ham.coef) and t_e < budget_s * 0.4:
+        one = W.Hamiltonian(n, ham.x[terms_done:terms_done + 1], ham.z[terms_done:terms_done + 1],
+                            ham.coef[terms_done:terms_done + 1])
+        t0 = time.perf_counter()
+        oracle.expectation(psi, one)
+        t_e += time.perf_counter() - t0
+        terms_done += 1
+    del psi
+    return dict(value=done / t_q, unit="gates/s", cores=oracle.threads(), kind="oracle",
+                sample=f"first {done} gates of the {n}-qubit circuit on a 2^{n} complex128 state "
+                       f"({t_q:.1f} s); EVC: {terms_done} Pauli strings ({t_e:.1f} s)",
+                evc_terms_per_s=terms_done / t_e)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="fabric30")
+    ap.add_argument("--dtype", default=None)
+    ap.add_argument("--tile-k", type=int, default=0)
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run only a plain 1 GiB device copy (traffic-counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_calib:
+        a = torch.empty(1 << 27, dtype=torch.complex64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8,
+                          "launches": 3}))
+        return
+    import paper_2410_04252_amd as P
+    import workloads as W
+    torch.cuda.set_device(0)
+    res = measure_main(P, W, torch, args)
+    res["workload"] = args.workload
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            tf = json.load(open(TRAFFIC_FILE))
+            if tf.get("source_hash") == kernel_source_hash() and tf.get("tile_k") == res["qsu"].get("tile_k", tf.get("tile_k")):
+                traffic = tf.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    res["roofline"]["traffic"] = traffic
+    grad = None if args.no_grad else measure_grad(P, W, torch, args)
+    cpu = None if args.no_cpu else measure_cpu(W, res, args.cpu_budget)
+    line = {
+        "metric": METRIC,
+        "value": round(res["qsu"]["gates_per_s"], 2),
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if res["dtype"] == "c64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_qubits": res["n"], "g_global": res["g"],
+                   "state": res["dtype"], "gates": res["m"], "pauli_terms": res["nt"],
+                   "ansatz": "fabric-style (Givens, Givens, CPHASE blocks), 16 brick layers",
+                   "hamiltonian": "Jordan-Wigner-like, coefficients N(0, 0.1)"},
+        "qsu": res["qsu"],
+        "evc": res["evc"],
+        "grad": grad,
+        "energy": res["energy"],
+        "roofline": res["roofline"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -100,7 +100,7 @@ typedef struct {
 } svq_stats;
 
 /* Create a state of n qubits (1 <= n <= 34), g emulated global qubits
- * (0 <= g < n, n - g >= 10), dtype c64 (float2, FP32 arithmetic) or c128
+ * (0 <= g < n, 8 <= n - g <= 32: a chunk holds at most 2^32 amplitudes), dtype c64 (float2, FP32 arithmetic) or c128
  * (double2).  dev_buf: borrowed device buffer of >= 2^n * 8 (c64) or 16
  * (c128) bytes that must outlive the handle, or NULL to let the library
  * allocate (and free on destroy).  The state starts as |0...0> with
@@ -188,6 +188,15 @@ svq_status sv_plan_paulis(int n, int g, const svq_pauli *terms, int n_terms, svq
                           int tile_k, int32_t *order_out, int32_t *qr_tile_out,
                           int32_t *pass_out, uint64_t *local_out, int32_t *n_qr_out,
                           int32_t *n_pass_out);
+
+/* Per-launch timing.  sv_profile(st, 1) clears the record and brackets every
+ * later kernel launch of the handle with HIP events on its stream;
+ * sv_profile(st, 0) stops recording.  sv_profile_read synchronises the stream
+ * and returns the number of recorded launches of one kind and their summed
+ * duration in ms.  Kinds: 0 gate pass, 1 QR pass, 2 EVC pass, 3 H|psi> pass,
+ * 4 adjoint pass. */
+svq_status sv_profile(svq_state st, int enable);
+svq_status sv_profile_read(svq_state st, int kind, int *count, double *total_ms);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *sv_last_error(void);

@@ -69,6 +69,8 @@ def lib():
         L.orc_adjoint_grad.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip, ip, dp, ip, ctypes.c_int,
                                        ctypes.c_int, up, up, dp, dp]
         L.orc_adjoint_grad.restype = ctypes.c_double
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -135,6 +137,22 @@ def apply_circuit(psi: np.ndarray, gates, theta) -> np.ndarray:
     if rc:
         raise ValueError("bad gate")
     return psi
+
+
+def apply_circuit_inplace(psi: np.ndarray, gates, theta) -> None:
+    """Like :func:`apply_circuit` but updates ``psi`` (complex128, contiguous)
+    in place; used to time the oracle without a full-state copy."""
+    n = int(psi.shape[0]).bit_length() - 1
+    kinds, qs, ang, _ = _gate_arrays(gates, theta)
+    rc = lib().orc_apply_circuit(_dp(psi.view(np.float64)), n, len(gates), _ip(kinds), _ip(qs),
+                                 _dp(ang), None)
+    if rc:
+        raise ValueError("bad gate")
+
+
+def threads() -> int:
+    """OpenMP threads the oracle runs with."""
+    return int(lib().orc_threads())
 
 
 def run_circuit(circ) -> np.ndarray:

@@ -28,6 +28,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -327,3 +328,6 @@ double orc_adjoint_grad(double *psi_ri, int n, int m, const int *kinds, const in
     free(lam);
     return E;
 }
+
+/* OpenMP threads used by the parallel loops above. */
+int orc_threads(void) { return omp_get_max_threads(); }

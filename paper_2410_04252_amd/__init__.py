@@ -52,7 +52,7 @@ class SvqError(RuntimeError):
 EXPORTS = ("sv_create", "sv_destroy", "sv_set_basis", "sv_set_amplitudes", "sv_get_amplitudes",
            "sv_get_layout", "sv_device_ptr", "sv_apply_circuit", "sv_qr_permute",
            "sv_expectation", "sv_apply_hamiltonian", "sv_grad", "sv_plan_circuit",
-           "sv_plan_paulis", "sv_last_error")
+           "sv_plan_paulis", "sv_profile", "sv_profile_read", "sv_last_error")
 
 
 def _load():
@@ -83,6 +83,8 @@ def _load():
     L.sv_plan_paulis.argtypes = [c_int, c_int, POINTER(svq_pauli), c_int, c_int, c_int,
                                  POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                  POINTER(c_uint64), POINTER(c_int32), POINTER(c_int32)]
+    L.sv_profile.argtypes = [vp, c_int]
+    L.sv_profile_read.argtypes = [vp, c_int, POINTER(c_int), POINTER(c_double)]
     L.sv_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "sv_last_error":
@@ -251,6 +253,20 @@ def sv_plan_paulis(n, g, ham, sched, tile_k=0):
     ng = len(set(int(x) for x in ham.x))
     return dict(order=list(order)[:ng], qr_tile=list(qt)[:ng], pass_=list(ps)[:ng],
                 local=list(loc)[:ng], n_qr=nqr.value, n_pass=npass.value)
+
+
+PROF_GATE, PROF_QR, PROF_EVC, PROF_HPSI, PROF_ADJ = 0, 1, 2, 3, 4
+
+
+def sv_profile(h, enable):
+    _check(lib.sv_profile(h, int(enable)))
+
+
+def sv_profile_read(h, kind):
+    c = c_int(0)
+    t = c_double(0.0)
+    _check(lib.sv_profile_read(h, kind, byref(c), byref(t)))
+    return c.value, t.value
 
 
 # ---------------------------------------------------------------------------

@@ -79,6 +79,15 @@ struct svq_state_s {
     std::map<std::string, std::unique_ptr<CachedPaulis>> pcache;
     DevBuf d_ops, d_partials, d_chunks, d_extra, d_lam, d_gpart, d_pptr, d_pgate, d_energy, d_grad;
     int device = 0;
+    // per-launch event timing (sv_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_rec;
+
+    ~svq_state_s() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
 
     bool dbl() const { return dtype == SVQ_C128; }
     size_t esz() const { return dbl() ? 16 : 8; }
@@ -87,6 +96,33 @@ struct svq_state_s {
 };
 
 namespace {
+
+hipEvent_t prof_event(svq_state st) {
+    if (st->ev_used == st->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        st->ev_pool.push_back(e);
+    }
+    return st->ev_pool[st->ev_used++];
+}
+
+// Bracket one launch of `kind` with events when profiling is on.
+struct ProfScope {
+    svq_state st;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(svq_state s, int k) : st(s), kind(k) {
+        if (!st->prof) return;
+        a = prof_event(st);
+        b = prof_event(st);
+        if (a) (void)hipEventRecord(a, st->stream);
+    }
+    ~ProfScope() {
+        if (!st->prof || !a || !b) return;
+        (void)hipEventRecord(b, st->stream);
+        st->prof_rec.push_back({kind, {a, b}});
+    }
+};
 
 svq_status hip_fail(svq_state st, hipError_t e, const char *what) {
     if (st) st->poisoned = true;
@@ -104,27 +140,62 @@ int default_k(const svq_state_s *st) {
     return std::max(8, std::min(13, std::min(k, st->n - st->g)));
 }
 
-int default_c(const svq_state_s *st) { return env_int("SVQ_LOW_BITS", 5); }
+int default_c(const svq_state_s *st) {
+    (void)st;
+    return env_int("SVQ_LOW_BITS", 4);
+}
+
+// Pauli passes are read-only: a wider tile covers more flip masks per read.
+int default_evc_k(const svq_state_s *st) {
+    int k = env_int("SVQ_EVC_K", st->dbl() ? 13 : 14);
+    return std::max(8, std::min(14, std::min(k, st->n - st->g)));
+}
+
+int default_evc_c(const svq_state_s *st) {
+    (void)st;
+    return env_int("SVQ_EVC_LOW_BITS", 4);
+}
 
 // Build the launch arguments of one QR step (disjoint transpositions).
 QrArgs make_qr_args(int n, bool dbl, const std::vector<Transposition> &tr) {
+    (void)dbl;
     QrArgs a;
     std::memset(&a, 0, sizeof(a));
+    int low = 64;
+    for (const auto &t : tr) low = std::min(low, std::min(t.a, t.b));
+    if (n >= 7 && low >= 6) {
+        a.rows_path = 1;
+        a.nrows = 1ULL << (n - 6);
+        for (const auto &t : tr) {
+            a.outer[2 * a.nouter] = (int8_t)t.a;
+            a.outer[2 * a.nouter + 1] = (int8_t)t.b;
+            a.nouter++;
+        }
+        return a;
+    }
     int partner[64];
     for (int i = 0; i < 64; ++i) partner[i] = -1;
     for (const auto &t : tr) {
         partner[t.a] = t.b;
         partner[t.b] = t.a;
     }
-    const int clow = std::min(n, dbl ? 5 : 6);
+    const int clow = std::min(n, 5);
     const int target = std::min(n, 10);
     uint64_t T = 0;
     for (int b = 0; b < clow; ++b) {
         T |= 1ULL << b;
         if (partner[b] >= 0) T |= 1ULL << partner[b];
     }
-    for (int b = 0; b < n && __builtin_popcountll(T) < target; ++b)
-        if (!((T >> b) & 1) && partner[b] < 0) T |= 1ULL << b;
+    // grow to `target` bits with unpaired bits or whole pairs, so that the
+    // tile stays closed under the involution
+    for (int b = 0; b < n && __builtin_popcountll(T) < target; ++b) {
+        if ((T >> b) & 1) continue;
+        if (partner[b] < 0) {
+            T |= 1ULL << b;
+        } else if (!((T >> partner[b]) & 1) && __builtin_popcountll(T) + 2 <= target) {
+            T |= (1ULL << b) | (1ULL << partner[b]);
+        }
+    }
     int j = 0;
     int tl[64];
     for (int b = 0; b < 64; ++b) tl[b] = -1;
@@ -165,6 +236,7 @@ double qr_bytes(const svq_state_s *st, const std::vector<Transposition> &tr) {
 svq_status run_qr(svq_state st, void *buf, const std::vector<Transposition> &tr) {
     if (tr.empty()) return SVQ_OK;
     QrArgs a = make_qr_args(st->n, st->dbl(), tr);
+    ProfScope ps(st, 1);
     HIPCHK(st, launch_qr(st->dbl(), buf, a, st->stream), "qr_permute");
     return SVQ_OK;
 }
@@ -290,6 +362,7 @@ svq_status run_circuit(svq_state st, CachedCircuit *cc, const std::vector<GateN>
             bytes += qr_bytes(st, s.qr);
         } else {
             const PassArgs &a = P.passes[s.idx];
+            ProfScope ps(st, 0);
             HIPCHK(st, launch_gate_pass(st->dbl(), P.k, false, st->buf, nullptr, a,
                                         (const PhaseDesc *)cc->d_phases.p,
                                         (const OpDesc *)st->d_ops.p, nullptr, a.nblocks,
@@ -312,7 +385,7 @@ svq_status run_circuit(svq_state st, CachedCircuit *cc, const std::vector<GateN>
 std::string pauli_key(const svq_pauli *terms, int nt, const svq_state_s *st, svq_sched sched,
                       int k, int c) {
     std::string key;
-    int hdr[5] = {st->n, st->g, (int)sched, k, c};
+    int hdr[6] = {st->n, st->g, (int)sched, k, c, st->dbl() ? 1 : 0};
     key.append((const char *)hdr, sizeof(hdr));
     for (int p : st->pos) key.append((const char *)&p, sizeof(p));
     key.append((const char *)terms, sizeof(svq_pauli) * (size_t)nt);
@@ -320,9 +393,10 @@ std::string pauli_key(const svq_pauli *terms, int nt, const svq_state_s *st, svq
 }
 
 svq_status get_pauli_plan(svq_state st, const svq_pauli *terms, int nt, svq_sched sched,
-                          CachedPaulis **out, double *ms_plan) {
-    const int k = default_k(st);
-    const int c = default_c(st);
+                          CachedPaulis **out, double *ms_plan, bool for_hpsi = false) {
+    // H|psi> keeps its FP64 accumulators in VGPRs: at most 2^13-wide tiles
+    const int k = for_hpsi ? std::min(default_evc_k(st), 13) : default_evc_k(st);
+    const int c = default_evc_c(st);
     std::string key = pauli_key(terms, nt, st, sched, k, c);
     auto it = st->pcache.find(key);
     if (it != st->pcache.end()) {
@@ -332,7 +406,7 @@ svq_status get_pauli_plan(svq_state st, const svq_pauli *terms, int nt, svq_sche
     }
     auto t0 = std::chrono::steady_clock::now();
     auto cp = std::make_unique<CachedPaulis>();
-    std::string err = plan_paulis(st->n, st->g, terms, nt, sched, k, c, 8, st->pos, cp->plan);
+    std::string err = plan_paulis(st->n, st->g, terms, nt, sched, k, c, st->dbl(), st->pos, cp->plan);
     if (!err.empty()) return fail(SVQ_EINVAL, err);
     PauliPlan &P = cp->plan;
     // wide groups are evaluated directly in the final layout
@@ -395,6 +469,7 @@ svq_status run_expectation(svq_state st, CachedPaulis *cp, double *energy_dev, d
             bytes += qr_bytes(st, s.qr);
         } else {
             const EvcPassArgs &a = P.passes[s.idx];
+            ProfScope ps(st, 2);
             HIPCHK(st, launch_evc_pass(st->dbl(), P.k, st->buf, a, (const EvcGroup *)cp->d_groups.p,
                                        (const EvcTerm *)cp->d_terms.p, (double *)st->d_partials.p,
                                        st->stream),
@@ -434,6 +509,31 @@ extern "C" {
 
 const char *sv_last_error(void) { return g_err.c_str(); }
 
+svq_status sv_profile(svq_state st, int enable) {
+    if (!st) return fail(SVQ_EINVAL, "null handle");
+    st->prof = enable != 0;
+    st->prof_rec.clear();
+    st->ev_used = 0;
+    return SVQ_OK;
+}
+
+svq_status sv_profile_read(svq_state st, int kind, int *count, double *total_ms) {
+    if (!st || !count || !total_ms) return fail(SVQ_EINVAL, "null argument");
+    HIPCHK(st, hipStreamSynchronize(st->stream), "sync");
+    int c = 0;
+    double t = 0.0;
+    for (auto &r : st->prof_rec) {
+        if (r.first != kind) continue;
+        float ms = 0.f;
+        HIPCHK(st, hipEventElapsedTime(&ms, r.second.first, r.second.second), "event time");
+        t += ms;
+        ++c;
+    }
+    *count = c;
+    *total_ms = t;
+    return SVQ_OK;
+}
+
 svq_status sv_create(int n, int g, svq_dtype dtype, void *dev_buf, size_t buf_bytes, void *stream,
                      svq_state *out) {
     if (!out) return fail(SVQ_EINVAL, "out is NULL");
@@ -441,6 +541,7 @@ svq_status sv_create(int n, int g, svq_dtype dtype, void *dev_buf, size_t buf_by
     if (n < 1 || n > 34) return fail(SVQ_EINVAL, "n must be in [1, 34]");
     if (g < 0 || g >= n) return fail(SVQ_EINVAL, "g must be in [0, n)");
     if (n - g < 8) return fail(SVQ_EINVAL, "need at least 8 chunk-local qubits (n - g >= 8)");
+    if (n - g > 32) return fail(SVQ_EINVAL, "at most 32 chunk-local qubits (n - g <= 32)");
     if (dtype != SVQ_C64 && dtype != SVQ_C128) return fail(SVQ_EINVAL, "bad dtype");
     auto st = std::make_unique<svq_state_s>();
     st->n = n;
@@ -594,7 +695,7 @@ svq_status sv_apply_hamiltonian(svq_state st, const svq_pauli *terms, int n_term
     if (n_terms < 0 || (n_terms > 0 && !terms)) return fail(SVQ_EINVAL, "bad term list");
     CachedPaulis *cp = nullptr;
     double ms = 0;
-    s = get_pauli_plan(st, terms, n_terms, SVQ_LAZY, &cp, &ms);
+    s = get_pauli_plan(st, terms, n_terms, SVQ_LAZY, &cp, &ms, true);
     if (s) return s;
     PauliPlan &P = cp->plan;
     // out follows psi's layout; its old content is overwritten
@@ -611,6 +712,7 @@ svq_status sv_apply_hamiltonian(svq_state st, const svq_pauli *terms, int n_term
         } else {
             HpsiPassArgs a = P.hpasses[stp.idx];
             a.accumulate = any ? 1 : 0;
+            ProfScope ps(st, 3);
             HIPCHK(st, launch_hpsi_pass(st->dbl(), P.k, nblocks, st->buf, out->buf, a,
                                         (const HpsiGroup *)cp->d_hgroups.p,
                                         (const HpsiTerm *)cp->d_hterms.p, st->stream),
@@ -708,6 +810,7 @@ svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *the
         } else {
             PassArgs a = P.passes[it->idx];
             a.gslot_base = 0;
+            ProfScope ps(st, 4);
             HIPCHK(st, launch_gate_pass(st->dbl(), P.k, true, st->buf, st->d_lam.p, a,
                                         (const PhaseDesc *)cc->d_phases.p, (const OpDesc *)st->d_ops.p,
                                         (double *)st->d_gpart.p, nblocks, st->stream),
@@ -764,7 +867,7 @@ static svq_status plan_common_circuit(int n, int g, const svq_gate *gates, int m
     for (int q = 0; q < n; ++q) pos[q] = q;
     int k = tile_k ? tile_k : 12;
     k = std::max(8, std::min(13, std::min(k, n - g)));
-    err = plan_circuit(n, g, gn, sched, k, gate_rb(k), env_int("SVQ_LOW_BITS", 5), pos, P);
+    err = plan_circuit(n, g, gn, sched, k, gate_rb(k), env_int("SVQ_LOW_BITS", 4), pos, P);
     if (!err.empty()) return fail(SVQ_EINVAL, err);
     return SVQ_OK;
 }
@@ -792,10 +895,10 @@ svq_status sv_plan_paulis(int n, int g, const svq_pauli *terms, int n_terms, svq
     if (n < 1 || n > 34 || g < 0 || g >= n || n - g < 8) return fail(SVQ_EINVAL, "bad n/g");
     std::vector<int> pos(n);
     for (int q = 0; q < n; ++q) pos[q] = q;
-    int k = tile_k ? tile_k : 12;
-    k = std::max(8, std::min(13, std::min(k, n - g)));
+    int k = tile_k ? tile_k : env_int("SVQ_EVC_K", 14);
+    k = std::max(8, std::min(14, std::min(k, n - g)));
     PauliPlan P;
-    std::string err = plan_paulis(n, g, terms, n_terms, sched, k, env_int("SVQ_LOW_BITS", 5), 8, pos, P);
+    std::string err = plan_paulis(n, g, terms, n_terms, sched, k, env_int("SVQ_EVC_LOW_BITS", 4), false, pos, P);
     if (!err.empty()) return fail(SVQ_EINVAL, err);
     for (size_t i = 0; i < P.order.size(); ++i) {
         if (order_out) order_out[i] = P.order[i];

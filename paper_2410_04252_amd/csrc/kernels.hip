@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -39,10 +40,6 @@ template <typename R, int NR> struct Regs {
     R re[NR], im[NR];
 };
 
-struct PhaseIdx {
-    uint32_t tt;   // tile-local index bits contributed by lane and wave
-};
-
 template <int NWB>
 __device__ __forceinline__ uint32_t thread_tile_index(const PhaseDesc &P, uint32_t lane,
                                                       uint32_t wave) {
@@ -63,117 +60,132 @@ __device__ __forceinline__ uint32_t reg_offset(const PhaseDesc &P, int j) {
     return r;
 }
 
+// Physical element offset of tile-local index t inside its tile.  Tile bits
+// are chunk-local and a chunk holds at most 2^32 elements, so 32 bits hold it.
 template <int K>
-__device__ __forceinline__ uint64_t tile_to_phys(uint32_t t, const int8_t *tphys) {
-    uint64_t p = 0;
+__device__ __forceinline__ uint32_t tile_to_phys(uint32_t t, const int8_t *tphys) {
+    uint32_t p = 0;
 #pragma unroll
     for (int j = 0; j < K; ++j)
-        if ((t >> j) & 1) p |= 1ULL << tphys[j];
+        if ((t >> j) & 1) p |= 1u << tphys[j];
     return p;
 }
 
-template <typename R, int NR, int RB>
-__device__ __forceinline__ void op_diag(Regs<R, NR> &v, uint32_t tt, const PhaseDesc &P,
-                                        const OpDesc &o) {
+// ---- gate ops on compile-time register bits -------------------------------
+
+template <int B, typename R, int NR>
+__device__ __forceinline__ void op_diag1(Regs<R, NR> &v, const OpDesc &o) {
     const R d0r = (R)o.m[0], d0i = (R)o.m[1], d1r = (R)o.m[2], d1i = (R)o.m[3];
-    const int pb = o.pbit;
-    const uint32_t cm = o.cmask;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
-        const uint32_t t = tt | reg_offset<RB>(P, j);
-        const bool b = (t >> pb) & 1u;
-        const bool c = (t & cm) == cm;
-        R dr = b ? d1r : d0r, di = b ? d1i : d0i;
-        dr = c ? dr : (R)1;
-        di = c ? di : (R)0;
+        const R dr = (j >> B) & 1 ? d1r : d0r, di = (j >> B) & 1 ? d1i : d0i;
         const R xr = v.re[j], xi = v.im[j];
         v.re[j] = xr * dr - xi * di;
         v.im[j] = xr * di + xi * dr;
     }
 }
 
-template <int B, typename R, int NR, int RB>
-__device__ __forceinline__ void op_mix1(Regs<R, NR> &v, uint32_t tt, const PhaseDesc &P,
-                                        const OpDesc &o) {
+template <int B0, int B1, typename R, int NR>
+__device__ __forceinline__ void op_cphase(Regs<R, NR> &v, const OpDesc &o) {
+    const R dr = (R)o.m[2], di = (R)o.m[3];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (!((j >> B0) & 1) || !((j >> B1) & 1)) continue;
+        const R xr = v.re[j], xi = v.im[j];
+        v.re[j] = xr * dr - xi * di;
+        v.im[j] = xr * di + xi * dr;
+    }
+}
+
+template <int B, typename R, int NR>
+__device__ __forceinline__ void op_mix1(Regs<R, NR> &v, const OpDesc &o) {
     const R a_r = (R)o.m[0], a_i = (R)o.m[1], b_r = (R)o.m[2], b_i = (R)o.m[3];
     const R c_r = (R)o.m[4], c_i = (R)o.m[5], d_r = (R)o.m[6], d_i = (R)o.m[7];
-    const uint32_t cm = o.cmask;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j & (1 << B)) continue;
         const int j1 = j | (1 << B);
-        const uint32_t t = tt | reg_offset<RB>(P, j);
-        const bool c = (t & cm) == cm;
         const R x0r = v.re[j], x0i = v.im[j], x1r = v.re[j1], x1i = v.im[j1];
-        const R y0r = a_r * x0r - a_i * x0i + b_r * x1r - b_i * x1i;
-        const R y0i = a_r * x0i + a_i * x0r + b_r * x1i + b_i * x1r;
-        const R y1r = c_r * x0r - c_i * x0i + d_r * x1r - d_i * x1i;
-        const R y1i = c_r * x0i + c_i * x0r + d_r * x1i + d_i * x1r;
-        v.re[j] = c ? y0r : x0r;
-        v.im[j] = c ? y0i : x0i;
-        v.re[j1] = c ? y1r : x1r;
-        v.im[j1] = c ? y1i : x1i;
+        v.re[j] = a_r * x0r - a_i * x0i + b_r * x1r - b_i * x1i;
+        v.im[j] = a_r * x0i + a_i * x0r + b_r * x1i + b_i * x1r;
+        v.re[j1] = c_r * x0r - c_i * x0i + d_r * x1r - d_i * x1i;
+        v.im[j1] = c_r * x0i + c_i * x0r + d_r * x1i + d_i * x1r;
     }
 }
 
-template <int B, typename R, int NR, int RB>
-__device__ __forceinline__ void op_xswap(Regs<R, NR> &v, uint32_t tt, const PhaseDesc &P,
-                                         const OpDesc &o) {
-    const uint32_t cm = o.cmask;
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-        if (j & (1 << B)) continue;
-        const int j1 = j | (1 << B);
-        const uint32_t t = tt | reg_offset<RB>(P, j);
-        const bool c = (t & cm) == cm;
-        const R x0r = v.re[j], x0i = v.im[j], x1r = v.re[j1], x1i = v.im[j1];
-        v.re[j] = c ? x1r : x0r;
-        v.im[j] = c ? x1i : x0i;
-        v.re[j1] = c ? x0r : x1r;
-        v.im[j1] = c ? x0i : x1i;
-    }
-}
-
-template <int B0, int B1, typename R, int NR, int RB>
-__device__ __forceinline__ void op_givens(Regs<R, NR> &v, uint32_t tt, const PhaseDesc &P,
-                                          const OpDesc &o) {
+template <int B, typename R, int NR>
+__device__ __forceinline__ void op_roty(Regs<R, NR> &v, const OpDesc &o) {
     const R cs = (R)o.m[0], sn = (R)o.m[1];
-    const uint32_t cm = o.cmask;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (j & (1 << B)) continue;
+        const int j1 = j | (1 << B);
+        const R x0r = v.re[j], x0i = v.im[j], x1r = v.re[j1], x1i = v.im[j1];
+        v.re[j] = cs * x0r - sn * x1r;
+        v.im[j] = cs * x0i - sn * x1i;
+        v.re[j1] = sn * x0r + cs * x1r;
+        v.im[j1] = sn * x0i + cs * x1i;
+    }
+}
+
+template <int B, typename R, int NR>
+__device__ __forceinline__ void op_xswap(Regs<R, NR> &v, const OpDesc &) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (j & (1 << B)) continue;
+        const int j1 = j | (1 << B);
+        const R tr = v.re[j], ti = v.im[j];
+        v.re[j] = v.re[j1];
+        v.im[j] = v.im[j1];
+        v.re[j1] = tr;
+        v.im[j1] = ti;
+    }
+}
+
+template <int B0, int B1, typename R, int NR>
+__device__ __forceinline__ void op_cnot(Regs<R, NR> &v, const OpDesc &) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (!((j >> B0) & 1) || ((j >> B1) & 1)) continue;
+        const int j1 = j | (1 << B1);
+        const R tr = v.re[j], ti = v.im[j];
+        v.re[j] = v.re[j1];
+        v.im[j] = v.im[j1];
+        v.re[j1] = tr;
+        v.im[j1] = ti;
+    }
+}
+
+template <int B0, int B1, typename R, int NR>
+__device__ __forceinline__ void op_givens(Regs<R, NR> &v, const OpDesc &o) {
+    const R cs = (R)o.m[0], sn = (R)o.m[1];
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j & ((1 << B0) | (1 << B1))) continue;
         const int ju = j | (1 << B0);   // b0 = 1, b1 = 0
         const int jw = j | (1 << B1);   // b0 = 0, b1 = 1
-        const uint32_t t = tt | reg_offset<RB>(P, j);
-        const bool c = (t & cm) == cm;
         const R ur = v.re[ju], ui = v.im[ju], wr = v.re[jw], wi = v.im[jw];
-        const R nur = cs * ur - sn * wr, nui = cs * ui - sn * wi;
-        const R nwr = sn * ur + cs * wr, nwi = sn * ui + cs * wi;
-        v.re[ju] = c ? nur : ur;
-        v.im[ju] = c ? nui : ui;
-        v.re[jw] = c ? nwr : wr;
-        v.im[jw] = c ? nwi : wi;
+        v.re[ju] = cs * ur - sn * wr;
+        v.im[ju] = cs * ui - sn * wi;
+        v.re[jw] = sn * ur + cs * wr;
+        v.im[jw] = sn * ui + cs * wi;
     }
 }
 
-template <int B0, int B1, typename R, int NR, int RB>
-__device__ __forceinline__ void op_mix2(Regs<R, NR> &v, uint32_t tt, const PhaseDesc &P,
-                                        const OpDesc &o) {
+template <int B0, int B1, typename R, int NR>
+__device__ __forceinline__ void op_mix2(Regs<R, NR> &v, const OpDesc &o) {
     R mr[16], mi[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         mr[e] = (R)o.m[2 * e];
         mi[e] = (R)o.m[2 * e + 1];
     }
-    const uint32_t cm = o.cmask;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j & ((1 << B0) | (1 << B1))) continue;
         int jl[4];
 #pragma unroll
         for (int l = 0; l < 4; ++l) jl[l] = j | ((l & 1) ? (1 << B0) : 0) | ((l & 2) ? (1 << B1) : 0);
-        const uint32_t t = tt | reg_offset<RB>(P, j);
-        const bool c = (t & cm) == cm;
         R xr[4], xi[4];
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
@@ -188,66 +200,60 @@ __device__ __forceinline__ void op_mix2(Regs<R, NR> &v, uint32_t tt, const Phase
                 sr += mr[r * 4 + cc] * xr[cc] - mi[r * 4 + cc] * xi[cc];
                 si += mr[r * 4 + cc] * xi[cc] + mi[r * 4 + cc] * xr[cc];
             }
-            v.re[jl[r]] = c ? sr : xr[r];
-            v.im[jl[r]] = c ? si : xi[r];
+            v.re[jl[r]] = sr;
+            v.im[jl[r]] = si;
         }
     }
 }
 
 // Dispatch on register-bit positions with explicit cases so that every
 // variant is inlined and the register arrays never leave VGPRs.
-#define SVQ_C1(FN, I)                                                   \
-    case I:                                                             \
-        if constexpr (I < RB) FN<I, R, NR, RB>(v, tt, P, o);            \
+#define SVQ_C1(FN, I)                                        \
+    case I:                                                  \
+        if constexpr (I < RB) FN<I, R, NR>(v, o);            \
         break;
-#define SVQ_C2(FN, I, J)                                                \
-    case I * 8 + J:                                                     \
-        if constexpr (I < RB && J < RB && I != J) FN<I, J, R, NR, RB>(v, tt, P, o); \
+#define SVQ_C2(FN, I, J)                                                      \
+    case I * 8 + J:                                                           \
+        if constexpr (I < RB && J < RB && I != J) FN<I, J, R, NR>(v, o);      \
         break;
 #define SVQ_ALL1(FN) SVQ_C1(FN, 0) SVQ_C1(FN, 1) SVQ_C1(FN, 2) SVQ_C1(FN, 3) SVQ_C1(FN, 4)
 #define SVQ_ROW(FN, I) SVQ_C2(FN, I, 0) SVQ_C2(FN, I, 1) SVQ_C2(FN, I, 2) SVQ_C2(FN, I, 3) SVQ_C2(FN, I, 4)
 #define SVQ_ALL2(FN) SVQ_ROW(FN, 0) SVQ_ROW(FN, 1) SVQ_ROW(FN, 2) SVQ_ROW(FN, 3) SVQ_ROW(FN, 4)
 
 template <typename R, int NR, int RB>
-__device__ __forceinline__ void apply_op(Regs<R, NR> &v, uint32_t tt, const PhaseDesc &P,
-                                         const OpDesc &o) {
+__device__ __forceinline__ void apply_op(Regs<R, NR> &v, const OpDesc &o) {
     static_assert(RB <= 5, "dispatch covers at most 5 register bits");
+    const int b2 = o.b0 * 8 + o.b1;
     switch (o.type) {
-    case OP_DIAG:
-        op_diag<R, NR, RB>(v, tt, P, o);
-        break;
-    case OP_MIX1:
-        switch (o.b0) { SVQ_ALL1(op_mix1) }
-        break;
-    case OP_XSWAP:
-        switch (o.b0) { SVQ_ALL1(op_xswap) }
-        break;
-    case OP_GIVENS:
-        switch (o.b0 * 8 + o.b1) { SVQ_ALL2(op_givens) }
-        break;
-    default:
-        switch (o.b0 * 8 + o.b1) { SVQ_ALL2(op_mix2) }
-        break;
+    case OP_DIAG1: switch (o.b0) { SVQ_ALL1(op_diag1) } break;
+    case OP_MIX1: switch (o.b0) { SVQ_ALL1(op_mix1) } break;
+    case OP_ROTY: switch (o.b0) { SVQ_ALL1(op_roty) } break;
+    case OP_XSWAP: switch (o.b0) { SVQ_ALL1(op_xswap) } break;
+    case OP_CPHASE: switch (b2) { SVQ_ALL2(op_cphase) } break;
+    case OP_CNOT: switch (b2) { SVQ_ALL2(op_cnot) } break;
+    case OP_GIVENS: switch (b2) { SVQ_ALL2(op_givens) } break;
+    default: switch (b2) { SVQ_ALL2(op_mix2) } break;
     }
 }
 
-// 2 Im <lambda|K|psi> over this thread's amplitudes, for the generator of o.
-template <int B0, int B1, typename R, int NR, int RB>
+// ---- adjoint: 2 Im <lambda|K|psi> over this thread's amplitudes ------------
+
+template <int B0, int B1, typename R, int NR>
 __device__ __forceinline__ double gen_value(const Regs<R, NR> &x, const Regs<R, NR> &l,
-                                           uint32_t tt, const PhaseDesc &P, const OpDesc &o) {
+                                            const OpDesc &o) {
     R acc = 0;
-    if (o.gtype == GEN_DIAG) {
+    if (o.gtype == GEN_DIAG1) {
         const R k0 = (R)o.k[0], k1 = (R)o.k[1];
-        const uint32_t cm = o.cmask;
-        const int pb = o.pbit;
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
-            const uint32_t t = tt | reg_offset<RB>(P, j);
-            const bool c = (t & cm) == cm;
-            const R kk = ((t >> pb) & 1u) ? k1 : k0;
-            // Im(conj(l) x) = l.re x.im - l.im x.re
-            const R im = l.re[j] * x.im[j] - l.im[j] * x.re[j];
-            acc += c ? kk * im : (R)0;
+            const R kk = ((j >> B0) & 1) ? k1 : k0;
+            acc += kk * (l.re[j] * x.im[j] - l.im[j] * x.re[j]);   // Im(conj(l) x)
+        }
+    } else if (o.gtype == GEN_CPHASE) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            if (!((j >> B0) & 1) || !((j >> B1) & 1)) continue;
+            acc -= l.re[j] * x.im[j] - l.im[j] * x.re[j];
         }
     } else if (o.gtype == GEN_MIX1) {
         const R k00r = (R)o.k[0], k00i = (R)o.k[1], k01r = (R)o.k[2], k01i = (R)o.k[3];
@@ -274,29 +280,21 @@ __device__ __forceinline__ double gen_value(const Regs<R, NR> &x, const Regs<R, 
     return 2.0 * (double)acc;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-#define SVQ_G1(I)                                                               \
-    case I:                                                                     \
-        if constexpr (I < RB) g = gen_value<I, 0, R, NR, RB>(x, l, tt, P, o);   \
+#define SVQ_G1(I)                                                          \
+    case I:                                                                \
+        if constexpr (I < RB) g = gen_value<I, 0, R, NR>(x, l, o);         \
         break;
-#define SVQ_G2(I, J)                                                            \
-    case I * 8 + J:                                                             \
-        if constexpr (I < RB && J < RB && I != J) g = gen_value<I, J, R, NR, RB>(x, l, tt, P, o); \
+#define SVQ_G2(I, J)                                                                   \
+    case I * 8 + J:                                                                    \
+        if constexpr (I < RB && J < RB && I != J) g = gen_value<I, J, R, NR>(x, l, o); \
         break;
 #define SVQ_GROW(I) SVQ_G2(I, 0) SVQ_G2(I, 1) SVQ_G2(I, 2) SVQ_G2(I, 3) SVQ_G2(I, 4)
 
 template <typename R, int NR, int RB>
 __device__ __forceinline__ double op_gradient(const Regs<R, NR> &x, const Regs<R, NR> &l,
-                                              uint32_t tt, const PhaseDesc &P, const OpDesc &o) {
+                                              const OpDesc &o) {
     double g = 0.0;
-    if (o.gtype == GEN_DIAG) {
-        g = gen_value<0, 0, R, NR, RB>(x, l, tt, P, o);
-    } else if (o.gtype == GEN_MIX1) {
+    if (o.gtype == GEN_DIAG1 || o.gtype == GEN_MIX1) {
         switch (o.b0) { SVQ_G1(0) SVQ_G1(1) SVQ_G1(2) SVQ_G1(3) SVQ_G1(4) }
     } else {
         switch (o.b0 * 8 + o.b1) { SVQ_GROW(0) SVQ_GROW(1) SVQ_GROW(2) SVQ_GROW(3) SVQ_GROW(4) }
@@ -304,117 +302,195 @@ __device__ __forceinline__ double op_gradient(const Regs<R, NR> &x, const Regs<R
     return g;
 }
 
-template <typename V, typename R, int NR>
-__device__ __forceinline__ void to_lds(V *lds, const Regs<R, NR> &v, uint32_t tt,
-                                       const uint32_t *roff) {
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
-    for (int j = 0; j < NR; ++j) {
-        V e;
-        e.x = v.re[j];
-        e.y = v.im[j];
-        lds[swz(tt | roff[j])] = e;
-    }
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
-template <typename V, typename R, int NR>
-__device__ __forceinline__ void from_lds(const V *lds, Regs<R, NR> &v, uint32_t tt,
-                                         const uint32_t *roff) {
+// ---- the pass ---------------------------------------------------------------
+
+// The maps register index j -> physical offset and j -> LDS slot are linear
+// over GF(2) (sums of disjoint bits; the swizzle is an XOR map), so they are
+// built from RB basis values instead of bit by bit.
+template <int RB, int K>
+struct RegMap {
+    uint32_t ph[RB];    // physical offset of register bit b
+    uint32_t sl[RB];    // LDS slot contribution of register bit b
+    __device__ __forceinline__ void init(const PhaseDesc &P, const int8_t *tphys) {
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            const int t = P.reg[b];
+            ph[b] = 1u << tphys[t];
+            sl[b] = swz(1u << t);
+        }
+    }
+    __device__ __forceinline__ uint32_t phys(int j) const {
+        uint32_t p = 0;
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+            if ((j >> b) & 1) p += ph[b];
+        return p;
+    }
+    __device__ __forceinline__ uint32_t slot(int j) const {
+        uint32_t p = 0;
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+            if ((j >> b) & 1) p ^= sl[b];
+        return p;
+    }
+};
+
+// Physical offset and LDS slot of the thread's own (lane, wave) bits.
+template <int NWB, int K>
+__device__ __forceinline__ void thread_maps(const PhaseDesc &P, const int8_t *tphys, uint32_t lane,
+                                            uint32_t wave, uint32_t &tp, uint32_t &tslot) {
+    uint32_t t = 0, p = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        const uint32_t bit = (lane >> b) & 1u;
+        t |= bit << P.lane[b];
+        p |= bit << tphys[P.lane[b]];
+    }
+#pragma unroll
+    for (int b = 0; b < NWB; ++b) {
+        const uint32_t bit = (wave >> b) & 1u;
+        t |= bit << P.wave[b];
+        p |= bit << tphys[P.wave[b]];
+    }
+    tp = p;
+    tslot = swz(t);
+}
+
+template <typename V, typename R, int NR, int RB, int K>
+__device__ __forceinline__ void load_regs(Regs<R, NR> &v, const V *__restrict__ src, uint32_t tp,
+                                          const RegMap<RB, K> &m) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
-        const V e = lds[swz(tt | roff[j])];
+        const V e = src[tp + m.phys(j)];
         v.re[j] = e.x;
         v.im[j] = e.y;
     }
 }
 
+template <typename V, typename R, int NR, int RB, int K>
+__device__ __forceinline__ void store_regs(const Regs<R, NR> &v, V *__restrict__ dst, uint32_t tp,
+                                           const RegMap<RB, K> &m) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        V e;
+        e.x = v.re[j];
+        e.y = v.im[j];
+        dst[tp + m.phys(j)] = e;
+    }
+}
+
 // One gate pass (forward), or one reverse adjoint pass when ADJ: psi and
-// lam both get U^dagger of every op in reverse order, and each parametric
-// op first records 2 Im <lam|K|psi> per wave into gpart.
-template <typename R, int K, int RB, bool ADJ>
+// lam both get U^dagger of every op in reverse order, and each parametric op
+// first records 2 Im <lam|K|psi> per wave into gpart.  The grid is
+// persistent: a block walks tiles tile = blockIdx.x, +gridDim.x, ... and
+// prefetches the next tile into registers while it works on the current one.
+template <typename R, int K, int RB, bool ADJ, bool PERSIST>
 __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
     typename V2T<R>::type *__restrict__ psi, typename V2T<R>::type *__restrict__ lam,
     const PassArgs a, const PhaseDesc *__restrict__ phases, const OpDesc *__restrict__ ops,
-    double *__restrict__ gpart, int nblocks_total) {
+    double *__restrict__ gpart, uint32_t ntiles) {
     using V = typename V2T<R>::type;
     constexpr int NR = 1 << RB;
     constexpr int NT = 1 << (K - RB);
+    constexpr int NW = NT / 64;
     constexpr int NWB = K - RB - 6;
+    // register prefetch of the next tile (persistent grid only)
+    constexpr bool PF = PERSIST && !(ADJ && sizeof(R) == 8);
     __shared__ V lds[(ADJ ? 2 : 1) << K];
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    const uint64_t base = spread(blockIdx.x, a.tphys, K);
-
     const int np = a.nphase;
-    const int p_first = ADJ ? np - 1 : 0;
-    const PhaseDesc *Pp = phases + a.phase0 + p_first;
-    uint32_t tt = thread_tile_index<NWB>(*Pp, lane, wave);
-    uint32_t roff[NR];
-#pragma unroll
-    for (int j = 0; j < NR; ++j) roff[j] = reg_offset<RB>(*Pp, j);
-
-    Regs<R, NR> v, w;
-    {
-        const uint64_t tp = tile_to_phys<K>(tt, a.tphys);
-#pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            const uint64_t addr = base + tp + tile_to_phys<K>(roff[j], a.tphys);
-            const V e = psi[addr];
-            v.re[j] = e.x;
-            v.im[j] = e.y;
-            if constexpr (ADJ) {
-                const V f = lam[addr];
-                w.re[j] = f.x;
-                w.im[j] = f.y;
-            }
-        }
+    const PhaseDesc &P0 = phases[a.phase0 + (ADJ ? np - 1 : 0)];   // load mapping
+    const PhaseDesc &PL = phases[a.phase0 + (ADJ ? 0 : np - 1)];   // store mapping
+    uint32_t tp0, ts0, tpL, tsL;
+    thread_maps<NWB, K>(P0, a.tphys, lane, wave, tp0, ts0);
+    thread_maps<NWB, K>(PL, a.tphys, lane, wave, tpL, tsL);
+    (void)tsL;
+    RegMap<RB, K> m0, mL;
+    m0.init(P0, a.tphys);
+    mL.init(PL, a.tphys);
+    uint32_t tile = blockIdx.x;
+    Regs<R, NR> nv, nw;
+    if (PF && tile < ntiles) {
+        const uint64_t base = spread(tile, a.tphys, K);
+        load_regs<V, R, NR, RB, K>(nv, psi + base, tp0, m0);
+        if constexpr (ADJ) load_regs<V, R, NR, RB, K>(nw, lam + base, tp0, m0);
     }
-    for (int s = 0; s < np; ++s) {
-        const int p = ADJ ? np - 1 - s : s;
-        if (s > 0) {
-            if (s > 1) __syncthreads();
-            to_lds<V, R, NR>(lds, v, tt, roff);
-            if constexpr (ADJ) to_lds<V, R, NR>(lds + (1 << K), w, tt, roff);
-            __syncthreads();
-            Pp = phases + a.phase0 + p;
-            tt = thread_tile_index<NWB>(*Pp, lane, wave);
-#pragma unroll
-            for (int j = 0; j < NR; ++j) roff[j] = reg_offset<RB>(*Pp, j);
-            from_lds<V, R, NR>(lds, v, tt, roff);
-            if constexpr (ADJ) from_lds<V, R, NR>(lds + (1 << K), w, tt, roff);
+    for (; tile < ntiles; tile += (PERSIST ? gridDim.x : ntiles)) {
+        const uint64_t base = spread(tile, a.tphys, K);
+        Regs<R, NR> v, w;
+        if constexpr (PF) {
+            v = nv;
+            if constexpr (ADJ) w = nw;
+            const uint32_t nt = tile + gridDim.x;
+            if (nt < ntiles) {
+                const uint64_t nbase = spread(nt, a.tphys, K);
+                load_regs<V, R, NR, RB, K>(nv, psi + nbase, tp0, m0);
+                if constexpr (ADJ) load_regs<V, R, NR, RB, K>(nw, lam + nbase, tp0, m0);
+            }
+        } else {
+            load_regs<V, R, NR, RB, K>(v, psi + base, tp0, m0);
+            if constexpr (ADJ) load_regs<V, R, NR, RB, K>(w, lam + base, tp0, m0);
         }
-        const int nop = Pp->nop;
-        const int op0 = Pp->op0;
-        for (int q = 0; q < nop; ++q) {
-            const int oi = op0 + (ADJ ? nop - 1 - q : q);
-            const OpDesc &o = ops[oi];
-            const PhaseDesc &P = *Pp;
-            if constexpr (ADJ) {
-                if (o.gtype != GEN_NONE) {
-                    const double gv = wave_sum(op_gradient<R, NR, RB>(v, w, tt, P, o));
-                    if (lane == 0)
-                        gpart[((size_t)o.gslot * nblocks_total + a.gslot_base + blockIdx.x) * (NT / 64) +
-                              wave] = gv;
+        uint32_t sw = ts0;
+        RegMap<RB, K> mc = m0;
+        for (int s = 0; s < np; ++s) {
+            const PhaseDesc &Pc = phases[a.phase0 + (ADJ ? np - 1 - s : s)];
+            if (s > 0) {
+                // transpose through LDS: write with the old mapping, read with the new
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    const uint32_t ad = sw ^ mc.slot(j);
+                    V e;
+                    e.x = v.re[j];
+                    e.y = v.im[j];
+                    lds[ad] = e;
+                    if constexpr (ADJ) {
+                        V f;
+                        f.x = w.re[j];
+                        f.y = w.im[j];
+                        lds[(1 << K) + ad] = f;
+                    }
                 }
-                apply_op<R, NR, RB>(w, tt, P, o);
-            }
-            apply_op<R, NR, RB>(v, tt, P, o);
-        }
-    }
-    {
-        const uint64_t tp = tile_to_phys<K>(tt, a.tphys);
+                __syncthreads();
+                uint32_t tpx;
+                thread_maps<NWB, K>(Pc, a.tphys, lane, wave, tpx, sw);
+                mc.init(Pc, a.tphys);
 #pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            const uint64_t addr = base + tp + tile_to_phys<K>(roff[j], a.tphys);
-            V e;
-            e.x = v.re[j];
-            e.y = v.im[j];
-            psi[addr] = e;
-            if constexpr (ADJ) {
-                V f;
-                f.x = w.re[j];
-                f.y = w.im[j];
-                lam[addr] = f;
+                for (int j = 0; j < NR; ++j) {
+                    const uint32_t ad = sw ^ mc.slot(j);
+                    const V e = lds[ad];
+                    v.re[j] = e.x;
+                    v.im[j] = e.y;
+                    if constexpr (ADJ) {
+                        const V f = lds[(1 << K) + ad];
+                        w.re[j] = f.x;
+                        w.im[j] = f.y;
+                    }
+                }
+            }
+            const int nop = Pc.nop;
+            const int op0 = Pc.op0;
+            for (int q = 0; q < nop; ++q) {
+                const OpDesc &o = ops[op0 + (ADJ ? nop - 1 - q : q)];
+                if constexpr (ADJ) {
+                    if (o.gtype != GEN_NONE) {
+                        const double gv = wave_sum(op_gradient<R, NR, RB>(v, w, o));
+                        if (lane == 0) gpart[((size_t)o.gslot * ntiles + tile) * NW + wave] = gv;
+                    }
+                    apply_op<R, NR, RB>(w, o);
+                }
+                apply_op<R, NR, RB>(v, o);
             }
         }
+        store_regs<V, R, NR, RB, K>(v, psi + base, tpL, mL);
+        if constexpr (ADJ) store_regs<V, R, NR, RB, K>(w, lam + base, tpL, mL);
     }
 }
 
@@ -422,46 +498,100 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
 // qubit reordering: in-place involution on physical bit positions
 // ---------------------------------------------------------------------------
 
-// Tile T = the low bits, their partners, and further unpaired bits; the
-// permutation maps tile b to tile pi(b) and permutes inside the tile.  A
-// block swaps the pair (b, pi(b)) once, through LDS so that both the loads
-// and the stores walk the low bits contiguously.
-template <typename V>
-__global__ __launch_bounds__(256) void k_qr(V *__restrict__ psi, const QrArgs a) {
-    extern __shared__ unsigned char smem[];
-    V *l0 = reinterpret_cast<V *>(smem);
-    V *l1 = l0 + (1 << a.tbits);
-    const int TS = 1 << a.tbits;
-    for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const uint64_t b = spread(tile, a.tphys, a.tbits);
-        uint64_t pb = b;
-        for (int i = 0; i < a.nouter; ++i) {
-            const int x = a.outer[2 * i], y = a.outer[2 * i + 1];
-            const uint64_t d = ((pb >> x) ^ (pb >> y)) & 1ULL;
-            pb ^= (d << x) | (d << y);
+// Swap the bit pairs pairs[0..np) of x (at most MAXP pairs; the loop bound
+// is a compile-time constant so the kernel-argument array stays in SGPRs).
+template <int MAXP>
+__device__ __forceinline__ uint64_t apply_pairs(uint64_t x, const int8_t *pairs, int np) {
+#pragma unroll
+    for (int i = 0; i < MAXP; ++i) {
+        if (i < np) {
+            const int a = pairs[2 * i], b = pairs[2 * i + 1];
+            const uint64_t d = ((x >> a) ^ (x >> b)) & 1ULL;
+            x ^= (d << a) | (d << b);
         }
+    }
+    return x;
+}
+
+// No exchanged bit below 6: rows of 64 consecutive elements map to rows, so
+// a wave swaps row r with row pi(r) (once, from the smaller side) with fully
+// coalesced loads and stores.  Each thread handles U rows per iteration so
+// that 2U loads are in flight before the first store.
+template <typename V, int U>
+__global__ __launch_bounds__(256) void k_qr_rows(V *__restrict__ psi, const QrArgs a) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t nrows = a.nrows;
+    const uint64_t wid = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint64_t stride = (uint64_t)gridDim.x * 4 * U;
+    for (uint64_t r0 = wid * U; r0 < nrows; r0 += stride) {
+        V x[U], y[U];
+        uint64_t ra[U], rb[U];
+        bool act[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t r = r0 + u;
+            const uint64_t pr = apply_pairs<32>(r << 6, a.outer, a.nouter) >> 6;
+            act[u] = r < nrows && r < pr;
+            ra[u] = (r << 6) | lane;
+            rb[u] = (pr << 6) | lane;
+            if (act[u]) {
+                x[u] = psi[ra[u]];
+                y[u] = psi[rb[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (act[u]) {
+                psi[ra[u]] = y[u];
+                psi[rb[u]] = x[u];
+            }
+        }
+    }
+}
+
+// General case: a tile T of TB bits holds the low bits, their partners and
+// further unpaired bits; pi maps tile b to tile pi(b) and permutes inside the
+// tile.  A block swaps the pair (b, pi(b)) once, through LDS so that loads and
+// stores both walk the low bits contiguously.
+template <typename V, int TB>
+__global__ __launch_bounds__(256) void k_qr_tiles(V *__restrict__ psi, const QrArgs a) {
+    constexpr int TS = 1 << TB;
+    constexpr int E = TS / 256;
+    __shared__ V l0[TS], l1[TS];
+    uint64_t off[E];
+    uint32_t perm[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t t = threadIdx.x + 256u * e;
+        uint64_t o = 0;
+#pragma unroll
+        for (int j = 0; j < TB; ++j)
+            if ((t >> j) & 1) o |= 1ULL << a.tphys[j];
+        off[e] = o;
+        perm[e] = (uint32_t)apply_pairs<16>(t, a.inner, a.ninner);
+    }
+    for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const uint64_t b = spread(tile, a.tphys, TB);
+        const uint64_t pb = apply_pairs<32>(b, a.outer, a.nouter);
         if (pb < b) continue;
         if (pb == b && a.ninner == 0) continue;
-        for (int t = threadIdx.x; t < TS; t += blockDim.x) {
-            uint64_t off = 0;
-            for (int j = 0; j < a.tbits; ++j)
-                if ((t >> j) & 1) off |= 1ULL << a.tphys[j];
-            uint32_t u = (uint32_t)t;
-            for (int i = 0; i < a.ninner; ++i) {
-                const int x = a.inner[2 * i], y = a.inner[2 * i + 1];
-                const uint32_t d = ((u >> x) ^ (u >> y)) & 1u;
-                u ^= (d << x) | (d << y);
-            }
-            l0[u] = psi[b + off];
-            if (pb != b) l1[u] = psi[pb + off];
+        V x[E], y[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            x[e] = psi[b + off[e]];
+            if (pb != b) y[e] = psi[pb + off[e]];
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            l0[perm[e]] = x[e];
+            if (pb != b) l1[perm[e]] = y[e];
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < TS; t += blockDim.x) {
-            uint64_t off = 0;
-            for (int j = 0; j < a.tbits; ++j)
-                if ((t >> j) & 1) off |= 1ULL << a.tphys[j];
-            psi[pb + off] = l0[t];
-            if (pb != b) psi[b + off] = l1[t];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t t = threadIdx.x + 256u * e;
+            psi[pb + off[e]] = l0[t];
+            if (pb != b) psi[b + off[e]] = l1[t];
         }
         __syncthreads();
     }
@@ -499,13 +629,37 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return s;
 }
 
+// Stage one tile into LDS: every thread issues all of its loads before the
+// first LDS write.  Thread bits are the tile's low bits (coalesced); the
+// offsets of the high part are uniform.
+template <typename V, int K, int TPB>
+__device__ __forceinline__ void stage_tile(V *lds, const V *__restrict__ src, const int8_t *tphys) {
+    constexpr int NT = 1 << TPB;
+    constexpr int E = 1 << (K - TPB);
+    const uint32_t tid = threadIdx.x;
+    uint32_t tp = 0;
+#pragma unroll
+    for (int b = 0; b < TPB; ++b) tp |= ((tid >> b) & 1u) << tphys[b];
+    V x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        uint32_t hp = 0;
+#pragma unroll
+        for (int b = 0; b < K - TPB; ++b)
+            if ((e >> b) & 1) hp |= 1u << tphys[TPB + b];
+        x[e] = src[tp + hp];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[tid + NT * e] = x[e];
+}
+
 template <typename R, int K>
-__global__ __launch_bounds__(1 << evc_tpb(K)) void k_evc_pass(
+__global__ __launch_bounds__(1 << evc_tpb(K, sizeof(R) == 8)) void k_evc_pass(
     const typename V2T<R>::type *__restrict__ psi, const EvcPassArgs a,
     const EvcGroup *__restrict__ groups, const EvcTerm *__restrict__ terms,
     double *__restrict__ partials) {
     using V = typename V2T<R>::type;
-    constexpr int TPB = evc_tpb(K);
+    constexpr int TPB = evc_tpb(K, sizeof(R) == 8);
     constexpr int NT = 1 << TPB;
     constexpr int TS = 1 << K;
     constexpr int Q = K - 1 - TPB;
@@ -513,13 +667,7 @@ __global__ __launch_bounds__(1 << evc_tpb(K)) void k_evc_pass(
     __shared__ V lds[TS];
     __shared__ double red[NT / 64];
     const uint64_t base = spread(blockIdx.x, a.tphys, K);
-    for (int t = threadIdx.x; t < TS; t += NT) {
-        uint64_t off = 0;
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            if ((t >> j) & 1) off |= 1ULL << a.tphys[j];
-        lds[t] = psi[base + off];
-    }
+    stage_tile<V, K, TPB>(lds, psi + base, a.tphys);
     __syncthreads();
     double acc = 0.0;
     for (int gi = 0; gi < a.ngroups; ++gi) {
@@ -582,13 +730,7 @@ __global__ __launch_bounds__(1 << hpsi_tpb(K)) void k_hpsi_pass(
     constexpr int NQ = 1 << QH;
     __shared__ V lds[TS];
     const uint64_t base = spread(blockIdx.x, a.tphys, K);
-    for (int t = threadIdx.x; t < TS; t += NT) {
-        uint64_t off = 0;
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            if ((t >> j) & 1) off |= 1ULL << a.tphys[j];
-        lds[t] = psi[base + off];
-    }
+    stage_tile<V, K, TPB>(lds, psi + base, a.tphys);
     __syncthreads();
     double lr[NQ], li[NQ];
 #pragma unroll
@@ -621,13 +763,16 @@ __global__ __launch_bounds__(1 << hpsi_tpb(K)) void k_hpsi_pass(
             li[jj] += (double)(f_r * p.y + f_i * p.x);
         }
     }
+    uint32_t tpo = 0;
+#pragma unroll
+    for (int b = 0; b < TPB; ++b) tpo |= ((tid >> b) & 1u) << a.tphys[b];
 #pragma unroll
     for (int jj = 0; jj < NQ; ++jj) {
-        const uint32_t t = tid | ((uint32_t)jj << TPB);
-        uint64_t off = 0;
+        uint32_t hp = 0;
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if ((t >> j) & 1) off |= 1ULL << a.tphys[j];
+        for (int b = 0; b < QH; ++b)
+            if ((jj >> b) & 1) hp |= 1u << a.tphys[TPB + b];
+        const uint64_t off = tpo + hp;
         V o;
         if (a.accumulate) {
             const V prev = lam[base + off];
@@ -803,27 +948,69 @@ static int grid_for(uint64_t N) {
     return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
 }
 
+static int g_num_cu = 0;
+
+static int num_cu() {
+    if (g_num_cu == 0) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            g_num_cu <= 0)
+            g_num_cu = 256;
+    }
+    return g_num_cu;
+}
+
+// Blocks of a persistent launch: resident blocks per CU times the CU count,
+// capped by the number of tiles.
+template <typename KF>
+static uint32_t persistent_grid(KF kern, int threads, uint64_t ntiles) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess ||
+        per_cu <= 0)
+        per_cu = 1;
+    const uint64_t g = (uint64_t)per_cu * num_cu();
+    return (uint32_t)(ntiles < g ? ntiles : g);
+}
+
+static int g_persist = -1;
+
+template <typename R, int KK, bool ADJ>
+static hipError_t launch_gate_k(void *psi, void *lam, const PassArgs &a, const PhaseDesc *ph,
+                                const OpDesc *ops, double *gpart, hipStream_t s) {
+    using V = typename V2T<R>::type;
+    constexpr int RB = gate_rb(KK);
+    constexpr int NT = 1 << (KK - RB);
+    if (g_persist < 0) {
+        const char *e = std::getenv("SVQ_PERSIST");
+        g_persist = (e && *e) ? std::atoi(e) : 0;
+    }
+    if constexpr (sizeof(R) * 2 * (ADJ ? 2 : 1) * (1 << KK) > 160 * 1024) {
+        return hipErrorInvalidValue;
+    } else {
+        const uint32_t ntiles = (uint32_t)a.nblocks;
+        if (g_persist) {
+            auto kern = k_gate_pass<R, KK, RB, ADJ, true>;
+            static uint32_t grid_cache = 0;
+            if (grid_cache == 0) grid_cache = persistent_grid(kern, NT, 1u << 30);
+            const uint32_t grid = ntiles < grid_cache ? ntiles : grid_cache;
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, s, (V *)psi, (V *)lam, a, ph, ops,
+                               gpart, ntiles);
+        } else {
+            hipLaunchKernelGGL((k_gate_pass<R, KK, RB, ADJ, false>), dim3(ntiles), dim3(NT), 0, s,
+                               (V *)psi, (V *)lam, a, ph, ops, gpart, ntiles);
+        }
+        return hipGetLastError();
+    }
+}
+
 template <typename R>
 static hipError_t launch_gate_t(int k, bool adj, void *psi, void *lam, const PassArgs &a,
-                                const PhaseDesc *ph, const OpDesc *ops, double *gpart, int nbt,
-                                int nblocks, hipStream_t s) {
-    using V = typename V2T<R>::type;
-    V *p = (V *)psi, *l = (V *)lam;
-#define SVQ_GATE_CASE(KK)                                                                      \
-    case KK:                                                                                   \
-        if (adj) {                                                                             \
-            if constexpr (sizeof(R) * 2 * 2 * (1 << KK) <= 160 * 1024)                         \
-                hipLaunchKernelGGL((k_gate_pass<R, KK, gate_rb(KK), true>), dim3(nblocks),     \
-                                   dim3(1 << (KK - gate_rb(KK))), 0, s, p, l, a, ph, ops,     \
-                                   gpart, nbt);                                                \
-            else                                                                               \
-                return hipErrorInvalidValue;                                                   \
-        } else {                                                                               \
-            hipLaunchKernelGGL((k_gate_pass<R, KK, gate_rb(KK), false>), dim3(nblocks),        \
-                               dim3(1 << (KK - gate_rb(KK))), 0, s, p, l, a, ph, ops, gpart,   \
-                               nbt);                                                           \
-        }                                                                                      \
-        break;
+                                const PhaseDesc *ph, const OpDesc *ops, double *gpart, hipStream_t s) {
+#define SVQ_GATE_CASE(KK)                                                                   \
+    case KK:                                                                                \
+        return adj ? launch_gate_k<R, KK, true>(psi, lam, a, ph, ops, gpart, s)             \
+                   : launch_gate_k<R, KK, false>(psi, lam, a, ph, ops, gpart, s);
     switch (k) {
         SVQ_GATE_CASE(8)
         SVQ_GATE_CASE(9)
@@ -835,24 +1022,37 @@ static hipError_t launch_gate_t(int k, bool adj, void *psi, void *lam, const Pas
         return hipErrorInvalidValue;
     }
 #undef SVQ_GATE_CASE
-    return hipGetLastError();
 }
 
 hipError_t launch_gate_pass(bool dbl, int k, bool adj, void *psi, void *lam, const PassArgs &a,
                             const PhaseDesc *ph, const OpDesc *ops, double *gpart, int nbt,
                             hipStream_t s) {
-    const int nblocks = a.nblocks;
-    return dbl ? launch_gate_t<double>(k, adj, psi, lam, a, ph, ops, gpart, nbt, nblocks, s)
-               : launch_gate_t<float>(k, adj, psi, lam, a, ph, ops, gpart, nbt, nblocks, s);
+    (void)nbt;
+    return dbl ? launch_gate_t<double>(k, adj, psi, lam, a, ph, ops, gpart, s)
+               : launch_gate_t<float>(k, adj, psi, lam, a, ph, ops, gpart, s);
 }
 
 hipError_t launch_qr(bool dbl, void *psi, const QrArgs &a, hipStream_t s) {
-    const size_t esz = dbl ? 16 : 8;
-    const size_t smem = 2 * ((size_t)1 << a.tbits) * esz;
-    uint64_t grid = a.ntiles < 4096 ? a.ntiles : 4096;
-    if (grid == 0) return hipSuccess;
-    if (dbl) hipLaunchKernelGGL(k_qr<double2>, dim3((unsigned)grid), dim3(256), smem, s, (double2 *)psi, a);
-    else hipLaunchKernelGGL(k_qr<float2>, dim3((unsigned)grid), dim3(256), smem, s, (float2 *)psi, a);
+    const int grid = 4 * num_cu();
+    if (a.rows_path) {
+        if (dbl) hipLaunchKernelGGL((k_qr_rows<double2, 4>), dim3(grid), dim3(256), 0, s, (double2 *)psi, a);
+        else hipLaunchKernelGGL((k_qr_rows<float2, 4>), dim3(grid), dim3(256), 0, s, (float2 *)psi, a);
+        return hipGetLastError();
+    }
+    const uint32_t g2 = (uint32_t)(a.ntiles < (uint64_t)grid ? a.ntiles : (uint64_t)grid);
+#define SVQ_QR_TB(TBV)                                                                                    \
+    case TBV:                                                                                             \
+        if (dbl) hipLaunchKernelGGL((k_qr_tiles<double2, TBV>), dim3(g2), dim3(256), 0, s, (double2 *)psi, a); \
+        else hipLaunchKernelGGL((k_qr_tiles<float2, TBV>), dim3(g2), dim3(256), 0, s, (float2 *)psi, a);       \
+        break;
+    switch (a.tbits) {
+        SVQ_QR_TB(8)
+        SVQ_QR_TB(9)
+        SVQ_QR_TB(10)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef SVQ_QR_TB
     return hipGetLastError();
 }
 
@@ -861,10 +1061,14 @@ static hipError_t launch_evc_t(int k, const void *psi, const EvcPassArgs &a, con
                                const EvcTerm *t, double *part, hipStream_t s) {
     using V = typename V2T<R>::type;
     const V *p = (const V *)psi;
-#define SVQ_EVC_CASE(KK)                                                                       \
-    case KK:                                                                                   \
-        hipLaunchKernelGGL((k_evc_pass<R, KK>), dim3(a.nblocks), dim3(1 << evc_tpb(KK)), 0, s, \
-                           p, a, g, t, part);                                                  \
+    constexpr bool D = sizeof(R) == 8;
+#define SVQ_EVC_CASE(KK)                                                                          \
+    case KK:                                                                                      \
+        if constexpr (sizeof(V) * (1 << KK) <= 128 * 1024)                                        \
+            hipLaunchKernelGGL((k_evc_pass<R, KK>), dim3(a.nblocks), dim3(1 << evc_tpb(KK, D)),   \
+                               0, s, p, a, g, t, part);                                           \
+        else                                                                                      \
+            return hipErrorInvalidValue;                                                          \
         break;
     switch (k) {
         SVQ_EVC_CASE(8)
@@ -873,6 +1077,7 @@ static hipError_t launch_evc_t(int k, const void *psi, const EvcPassArgs &a, con
         SVQ_EVC_CASE(11)
         SVQ_EVC_CASE(12)
         SVQ_EVC_CASE(13)
+        SVQ_EVC_CASE(14)
     default:
         return hipErrorInvalidValue;
     }

@@ -10,11 +10,12 @@ namespace svq {
 
 // In-place relayout by disjoint transpositions of physical bits.
 struct QrArgs {
-    int32_t tbits;          // tile bits
-    int32_t nouter;         // transpositions with both bits outside the tile
+    int32_t tbits;          // tile bits (tile path)
+    int32_t nouter;         // transpositions outside the tile (rows path: all of them)
     int32_t ninner;         // transpositions inside the tile (tile-local bits)
-    int32_t pad;
+    int32_t rows_path;      // 1: no exchanged bit below 6, swap rows of 64 elements
     uint64_t ntiles;        // 2^(n - tbits)
+    uint64_t nrows;         // 2^(n - 6)
     int8_t tphys[16];       // physical bit of tile-local bit j (ascending)
     int8_t outer[64];       // pairs (a, b) of physical bits
     int8_t inner[32];       // pairs (a, b) of tile-local bits

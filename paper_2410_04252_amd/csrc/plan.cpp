@@ -367,17 +367,17 @@ static void assign_lanes(int k, uint32_t regs, PhaseDesc &P) {
     // order by residue so lane bit b has residue b where possible
     std::stable_sort(lanes, lanes + nl, [](int a, int b) { return a % 6 < b % 6; });
     for (int i = 0; i < 8; ++i) P.lane[i] = 0;
-    for (int i = 0; i < nl; ++i) P.lane[i] = (int8_t)lanes[i];
+    for (int i = 0; i < nl; ++i) P.lane[i] = lanes[i];
     int nw = 0;
     for (int i = 0; i < 8; ++i) P.wave[i] = 0;
     for (int b = 0; b < k; ++b)
-        if (!((taken >> b) & 1)) P.wave[nw++] = (int8_t)b;
+        if (!((taken >> b) & 1)) P.wave[nw++] = b;
 }
 
 static void set_regs(uint32_t regs, int rb, PhaseDesc &P) {
     int j = 0;
     for (int i = 0; i < 8; ++i) P.reg[i] = 0;
-    for (uint32_t r = regs; r && j < rb; r &= r - 1) P.reg[j++] = (int8_t)__builtin_ctz(r);
+    for (uint32_t r = regs; r && j < rb; r &= r - 1) P.reg[j++] = __builtin_ctz(r);
 }
 
 struct L3Gate {
@@ -390,10 +390,16 @@ struct L3Gate {
 
 static int op_type_of(int kind) {
     switch (kind) {
-    case SVQ_Z: case SVQ_S: case SVQ_T: case SVQ_RZ: case SVQ_CZ: case SVQ_CPHASE:
-        return OP_DIAG;
-    case SVQ_X: case SVQ_CNOT:
+    case SVQ_Z: case SVQ_S: case SVQ_T: case SVQ_RZ:
+        return OP_DIAG1;
+    case SVQ_CZ: case SVQ_CPHASE:
+        return OP_CPHASE;
+    case SVQ_X:
         return OP_XSWAP;
+    case SVQ_CNOT:
+        return OP_CNOT;
+    case SVQ_RY:
+        return OP_ROTY;
     case SVQ_GIVENS:
         return OP_GIVENS;
     case SVQ_SWAP: case SVQ_U2:
@@ -462,10 +468,10 @@ static void plan_phases(int k, int rb, const std::vector<L3Gate> &gs, CircuitPla
         set_regs(ph.regs, rb, D);
         if (lanes_ok(ph.regs)) {
             // keep lanes on bits 0..5 (coalesced global access)
-            for (int i = 0; i < 6; ++i) D.lane[i] = (int8_t)i;
+            for (int i = 0; i < 6; ++i) D.lane[i] = i;
             int nw = 0;
             for (int b = 6; b < k; ++b)
-                if (!((ph.regs >> b) & 1)) D.wave[nw++] = (int8_t)b;
+                if (!((ph.regs >> b) & 1)) D.wave[nw++] = b;
         } else {
             assign_lanes(k, ph.regs, D);
         }
@@ -480,15 +486,10 @@ static void plan_phases(int k, int rb, const std::vector<L3Gate> &gs, CircuitPla
             std::memset(&o, 0, sizeof(o));
             o.gslot = -1;
             o.type = op_type_of(g.kind);
-            o.cmask = g.ctrl;
-            o.pbit = g.diag;
-            o.b0 = o.b1 = 0;
-            if (o.type == OP_MIX1 || o.type == OP_XSWAP) {
-                o.b0 = regpos[g.kind == SVQ_CNOT ? g.tq1 : g.tq0];
-            } else if (o.type == OP_GIVENS || o.type == OP_MIX2) {
-                o.b0 = regpos[g.tq0];
-                o.b1 = regpos[g.tq1];
-            }
+            o.cmask = 0;
+            o.pbit = -1;
+            o.b0 = regpos[g.tq0];
+            o.b1 = g.tq1 >= 0 ? regpos[g.tq1] : 0;
             P.ops.push_back(o);
             P.op_gate.push_back(g.gate);
         }
@@ -563,7 +564,7 @@ std::string plan_circuit(int n, int g, const std::vector<GateN> &gates, svq_sche
                 x.tq0 = first_bit(to_tile(bit(lay[gt.q[0]]), S));
                 x.tq1 = gt.nq > 1 ? first_bit(to_tile(bit(lay[gt.q[1]]), S)) : -1;
                 x.t = to_tile(pt[i], S);
-                x.mix = to_tile(phys_mask(gt.mixmask, lay), S);
+                x.mix = x.t;   // every qubit of the gate is a register bit
                 x.ctrl = to_tile(phys_mask(gt.ctrlmask, lay), S);
                 x.diag = gt.diag_q >= 0 ? first_bit(to_tile(bit(lay[gt.diag_q]), S)) : -1;
                 l3.push_back(x);
@@ -622,7 +623,7 @@ void fill_ops(const std::vector<GateN> &gates, const double *theta, const std::v
             o.gtype = GEN_MIX1; set_c(o.k, 1, 0.5, 0); set_c(o.k, 2, 0.5, 0);
             break;
         case SVQ_RY:
-            set_c(m, 0, c, 0); set_c(m, 1, -s, 0); set_c(m, 2, s, 0); set_c(m, 3, c, 0);
+            m[0] = c; m[1] = s;
             o.gtype = GEN_MIX1; set_c(o.k, 1, 0, -0.5); set_c(o.k, 2, 0, 0.5);
             break;
         case SVQ_U1:
@@ -632,14 +633,14 @@ void fill_ops(const std::vector<GateN> &gates, const double *theta, const std::v
         case SVQ_S: set_c(m, 0, 1, 0); set_c(m, 1, 0, 1); break;
         case SVQ_T: set_c(m, 0, 1, 0); set_c(m, 1, r2, r2); break;
         case SVQ_RZ:
-            set_c(m, 0, std::cos(0.5 * t), -std::sin(0.5 * t));
-            set_c(m, 1, std::cos(0.5 * t), std::sin(0.5 * t));
-            o.gtype = GEN_DIAG; o.k[0] = 0.5; o.k[1] = -0.5;
+            set_c(m, 0, c, -s);
+            set_c(m, 1, c, s);
+            o.gtype = GEN_DIAG1; o.k[0] = 0.5; o.k[1] = -0.5;
             break;
-        case SVQ_CZ: set_c(m, 0, 1, 0); set_c(m, 1, -1, 0); break;
+        case SVQ_CZ: set_c(m, 1, -1, 0); break;
         case SVQ_CPHASE:
-            set_c(m, 0, 1, 0); set_c(m, 1, std::cos(t), std::sin(t));
-            o.gtype = GEN_DIAG; o.k[0] = 0.0; o.k[1] = -1.0;
+            set_c(m, 1, std::cos(t), std::sin(t));
+            o.gtype = GEN_CPHASE;
             break;
         case SVQ_GIVENS:
             m[0] = c; m[1] = s;
@@ -651,17 +652,20 @@ void fill_ops(const std::vector<GateN> &gates, const double *theta, const std::v
         case SVQ_U2:
             for (int j = 0; j < 32; ++j) m[j] = g.mat[j];
             break;
-        default:   // X, CNOT: pure swap
+        default:   // X, CNOT: pure swaps
             break;
         }
+        if (g.param < 0) o.gtype = GEN_NONE;
         if (!inverse) continue;
-        // U^dagger
-        if (o.type == OP_DIAG) {
+        switch (o.type) {   // U^dagger
+        case OP_DIAG1: case OP_CPHASE:
             m[1] = -m[1];
             m[3] = -m[3];
-        } else if (o.type == OP_GIVENS) {
+            break;
+        case OP_GIVENS: case OP_ROTY:
             m[1] = -m[1];
-        } else if (o.type == OP_MIX1 || o.type == OP_MIX2) {
+            break;
+        case OP_MIX1: case OP_MIX2: {
             const int d = o.type == OP_MIX1 ? 2 : 4;
             double tmp[32];
             for (int r = 0; r < d; ++r)
@@ -670,6 +674,10 @@ void fill_ops(const std::vector<GateN> &gates, const double *theta, const std::v
                     tmp[2 * (r * d + cc) + 1] = -m[2 * (cc * d + r) + 1];
                 }
             std::memcpy(m, tmp, sizeof(double) * 2 * d * d);
+            break;
+        }
+        default:
+            break;
         }
     }
 }
@@ -678,7 +686,7 @@ void fill_ops(const std::vector<GateN> &gates, const double *theta, const std::v
 // Pauli plan
 // ---------------------------------------------------------------------------
 
-static uint32_t pext32(uint32_t v, const int8_t *bits, int nb) {
+static uint32_t pext32(uint32_t v, const int32_t *bits, int nb) {
     uint32_t out = 0;
     for (int i = 0; i < nb; ++i)
         if ((v >> bits[i]) & 1) out |= 1u << i;
@@ -686,7 +694,7 @@ static uint32_t pext32(uint32_t v, const int8_t *bits, int nb) {
 }
 
 std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched sched, int k,
-                        int c, int tpb_log2, const std::vector<int> &pos0, PauliPlan &out) {
+                        int c, bool dbl, const std::vector<int> &pos0, PauliPlan &out) {
     out = PauliPlan();
     out.n = n;
     out.g = g;
@@ -774,8 +782,7 @@ std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched 
     // by intervening reorders); it is evaluated once, in its first tile.
     std::vector<char> done(ng, 0);
 
-    (void)tpb_log2;
-    const int TPB = evc_tpb(keff);     // EVC threads per tile (log2)
+    const int TPB = evc_tpb(keff, dbl);   // EVC threads per tile (log2)
     const int Q = keff - 1 - TPB;      // EVC cube bits (half space)
     const int TPBH = hpsi_tpb(keff);   // H|psi> threads per tile (log2)
     const int QH = keff - TPBH;        // H|psi> cube bits (full space)
@@ -887,8 +894,8 @@ std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched 
                 int nb = 0;
                 for (int b = 0; b < keff; ++b) {
                     if (b == G.hbit) continue;
-                    if (nb < TPB) G.tbits[nb] = (int8_t)b;
-                    else G.wbits[nb - TPB] = (int8_t)b;
+                    if (nb < TPB) G.tbits[nb] = b;
+                    else G.wbits[nb - TPB] = b;
                     ++nb;
                 }
                 uint32_t tmask = 0;

@@ -121,7 +121,8 @@ struct PauliPlan {
     int total_blocks = 0;                    // sum of blocks over passes (partials)
 };
 
+// dbl selects the EVC thread geometry of the complex128 kernels.
 std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched sched, int k,
-                        int c, int tpb_log2, const std::vector<int> &pos0, PauliPlan &out);
+                        int c, bool dbl, const std::vector<int> &pos0, PauliPlan &out);
 
 }  // namespace svq

@@ -22,27 +22,35 @@ constexpr int kLaneBits = 6;      // wave64
 // wave per tile).
 constexpr int gate_rb(int k) { return k - 6 < 4 ? k - 6 : 4; }
 // Threads (log2) of a Pauli pass: every thread owns a 2^(k-1-tpb) cube of
-// the half space (EVC) or a 2^(k-tpb) cube of outputs (H|psi>).
-constexpr int evc_tpb(int k) { return k - 5 > 6 ? k - 5 : 6; }
+// the half space (EVC) or a 2^(k-tpb) cube of outputs (H|psi>).  Double
+// precision keeps one cube bit fewer so the Walsh arrays stay in VGPRs.
+constexpr int evc_tpb(int k, bool dbl = false) {
+    return (dbl ? k - 4 : k - 5) > 6 ? (dbl ? k - 4 : k - 5) : 6;
+}
 constexpr int hpsi_tpb(int k) { return k - 4 > 6 ? k - 4 : 6; }
 
-// Gate-pass operations.  b0/b1 are register-bit positions of the mixing
-// qubits (b0 = the gate matrix's local bit 0), pbit a tile-local bit, cmask
-// tile-local control bits that must all be 1.
+// Gate-pass operations.  Every qubit of a gate is a register bit in the
+// phase that applies it, so b0/b1 (register-bit positions; b0 = the gate
+// matrix's local bit 0, for controlled gates the control) are compile-time
+// values after dispatch and no per-amplitude index test is needed.
 enum OpType : int32_t {
-    OP_DIAG = 0,    // amp *= (bit pbit ? d1 : d0);        m = {d0.re, d0.im, d1.re, d1.im}
-    OP_MIX1 = 1,    // 2x2 dense on register bit b0;        m = row-major complex 2x2
-    OP_XSWAP = 2,   // swap along register bit b0 (X / CNOT)
+    OP_DIAG1 = 0,   // amp *= (bit b0 ? d1 : d0);               m = {d0.re, d0.im, d1.re, d1.im}
+    OP_MIX1 = 1,    // 2x2 dense on b0;                          m = row-major complex 2x2
+    OP_XSWAP = 2,   // swap along b0 (X)
     OP_GIVENS = 3,  // real rotation of (|b0=1,b1=0>, |b0=0,b1=1>); m = {c, s}
-    OP_MIX2 = 4,    // 4x4 dense on register bits (b0, b1);  m = row-major complex 4x4
+    OP_MIX2 = 4,    // 4x4 dense on (b0, b1);                    m = row-major complex 4x4
+    OP_CPHASE = 5,  // amp *= d1 where both bits are set;        m = {-, -, d1.re, d1.im}
+    OP_CNOT = 6,    // swap along b1 where b0 is set
+    OP_ROTY = 7,    // real 2x2 [[c, -s], [s, c]] on b0;         m = {c, s}
 };
 
 // Generator K of a parametric op (U = exp(-i t K)), for the adjoint sweep.
 enum GenType : int32_t {
     GEN_NONE = 0,
-    GEN_DIAG = 1,    // diagonal on pbit with control cmask: k = {k0, k1} (real)
+    GEN_DIAG1 = 1,   // diag(k0, k1) on b0 (real)
     GEN_MIX1 = 2,    // 2x2 Hermitian on b0: k = row-major complex 2x2
     GEN_GIVENS = 3,  // (X_b0 Y_b1 - Y_b0 X_b1)/4
+    GEN_CPHASE = 4,  // -|11><11| on (b0, b1)
 };
 
 struct OpDesc {
@@ -57,10 +65,13 @@ struct OpDesc {
     double k[8];
 };
 
+// Device-resident descriptors use 32-bit fields only: gfx9 scalar loads are
+// dword-granular, and a sub-dword field would be fetched by a vector load
+// whose vmcnt wait also stalls on the tile's outstanding global loads.
 struct PhaseDesc {
-    int8_t reg[8];    // tile-local bit of register bit b
-    int8_t lane[8];   // tile-local bit of lane bit b (6 used)
-    int8_t wave[8];   // tile-local bit of wave bit b
+    int32_t reg[8];   // tile-local bit of register bit b
+    int32_t lane[8];  // tile-local bit of lane bit b (6 used)
+    int32_t wave[8];  // tile-local bit of wave bit b
     int32_t op0, nop;
 };
 
@@ -77,8 +88,8 @@ struct EvcGroup {
     uint32_t xl;          // tile-local flip mask (0 for the diagonal group)
     int32_t hbit;         // tile-local half-space bit (the pair partner flips it)
     int32_t t0, nt;       // term range
-    int8_t tbits[16];     // tile-local bits of the thread index (low to high)
-    int8_t wbits[8];      // tile-local bits of the per-thread cube index
+    int32_t tbits[16];    // tile-local bits of the thread index (low to high)
+    int32_t wbits[8];     // tile-local bits of the per-thread cube index
     int32_t need;         // bit0: real array used, bit1: imaginary array used
     int32_t pad;
 };

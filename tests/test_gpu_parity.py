@@ -142,3 +142,24 @@ def test_grad_parity_small(P):
         assert abs(e - e_ref) <= _tol_energy(e_ref, ham, 1e-6 if dtype == "c64" else 1e-12)
         assert np.linalg.norm(grad - g_ref) <= rel * np.linalg.norm(g_ref)
         st.close()
+
+
+def test_qr_many_pairs_small_n(P):
+    """Relayouts that pair most bits (tile of the QR kernel filled with whole
+    pairs) on the smallest states."""
+    import torch
+    for n, g in ((8, 0), (9, 1), (10, 2), (11, 3)):
+        rng = np.random.default_rng(100 + n)
+        v = W.random_state(n, 7 + n, np.complex64)
+        buf = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+        st = P.State(n, g, "c64", buf=buf)
+        st.set_amplitudes(v)
+        pos = list(range(n))
+        for _ in range(3):
+            new = [int(x) for x in rng.permutation(n)]
+            before = buf.cpu().numpy().copy()
+            st.qr_permute(new)
+            torch.cuda.synchronize()
+            assert np.array_equal(buf.cpu().numpy(), oracle.qr_permute(before, pos, new))
+            pos = new
+        st.close()
