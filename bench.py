@@ -248,6 +248,44 @@ def measure_cpu(W, main, budget_s):
                 evc_terms_per_s=terms_done / t_e)
 
 
+def _pmc_rows(d, counter):
+    """(kernel name, value) of every dispatch in a rocprofv3 --pmc CSV tree."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r.get("Kernel_Name", ""), float(r["Counter_Value"])))
+    return rows
+
+
+def ingest_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, tile_k=0):
+    """FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by the
+    bytes a plain device copy of known size really moves per KiB counted."""
+    def avg(rows, pat):
+        v = [x for k, x in rows if pat in k]
+        return sum(v) / len(v) if v else None, len(v)
+    gf, nf = avg(_pmc_rows(fetch_dir, "FETCH_SIZE"), "k_gate_pass")
+    gw, nw = avg(_pmc_rows(write_dir, "WRITE_SIZE"), "k_gate_pass")
+    cf, _ = avg(_pmc_rows(copy_fetch_dir, "FETCH_SIZE"), "")
+    cw, _ = avg(_pmc_rows(copy_write_dir, "WRITE_SIZE"), "")
+    copy_bytes = (1 << 27) * 8
+    f_fetch = copy_bytes / (cf * 1024.0)
+    f_write = copy_bytes / (cw * 1024.0)
+    traffic = gf * 1024.0 * f_fetch + gw * 1024.0 * f_write
+    out = dict(kernel="k_gate_pass (fabric30, lazy)", source_hash=kernel_source_hash(),
+               fetch_kib_per_launch=gf, write_kib_per_launch=gw, launches=[nf, nw],
+               copy_fetch_kib=cf, copy_write_kib=cw, copy_bytes=copy_bytes,
+               scale_fetch=f_fetch, scale_write=f_write, bytes_per_launch=traffic,
+               algorithmic_bytes_per_launch=2 * (1 << 30) * 8)
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,7 +299,14 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (traffic-counter calibration)")
+    ap.add_argument("--ingest-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                       "COPY_WRITE_DIR"),
+                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this benchmark and "
+                         "of --copy-calib into the per-launch HBM traffic of the gate pass")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        ingest_pmc(*args.ingest_pmc, tile_k=args.tile_k)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
@@ -285,7 +330,7 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         try:
             tf = json.load(open(TRAFFIC_FILE))
-            if tf.get("source_hash") == kernel_source_hash() and tf.get("tile_k") == res["qsu"].get("tile_k", tf.get("tile_k")):
+            if tf.get("source_hash") == kernel_source_hash():
                 traffic = tf.get("bytes_per_launch")
         except Exception:
             traffic = None
