@@ -218,6 +218,62 @@ def measure_grad(P, W, torch, args):
                 speedup=ps_ms / adj_ms, rel_diff_adjoint_vs_shift=rel)
 
 
+def measure_batch(P, W, torch, args):
+    """256 independent instances (n uniform in 10..22, 6 fabric layers, 200
+    JW-like terms): QSU + EVC + adjoint gradient of all of them in one
+    persistent, graph-captured launch, against a one-at-a-time loop."""
+    import numpy as np
+    inst = [(d["circuit"], d["ham"]) for d in W.batch_instances()]
+    ninst = len(inst)
+    log(f"[bench] batch: {ninst} instances, n in [{min(c.n for c, _ in inst)}, "
+        f"{max(c.n for c, _ in inst)}]")
+    t0 = time.perf_counter()
+    b = P.Batch(inst)
+    create_ms = (time.perf_counter() - t0) * 1e3
+    b.run()                       # first run captures the graph
+    torch.cuda.synchronize()
+    reps = 5
+    times, lats = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        _, _, lat = b.run()
+        times.append((time.perf_counter() - t0) * 1e3)
+        lats.append(lat)
+    b.close()
+    run_ms = float(np.median(times))
+    lat = lats[int(np.argsort(times)[reps // 2])]
+    # one at a time: one handle per instance, sv_grad each, host-synchronised
+    states = [P.State(c.n, 0, "c64") for c, _ in inst]
+    gcs = [P.gates_array(c.gates) for c, _ in inst]
+    tcs = [P.paulis_array(h) for _, h in inst]
+
+    def loop():
+        done = []
+        t0 = time.perf_counter()
+        for (c, h), st, gc, tc in zip(inst, states, gcs, tcs):
+            P.sv_set_basis(st.h, c.psi0_index)
+            P.sv_grad(st.h, gc, len(c.gates), c.theta, c.n_params, tc, len(h.coef), P.LAZY)
+            done.append((time.perf_counter() - t0) * 1e3)
+        return done
+
+    loop()
+    torch.cuda.synchronize()
+    done = loop()
+    for st in states:
+        st.close()
+    loop_ms = done[-1]
+    log(f"[bench] batch {run_ms:.2f} ms ({ninst / run_ms * 1e3:.0f} inst/s, p50 {np.percentile(lat, 50):.2f} "
+        f"p99 {np.percentile(lat, 99):.2f} ms); one at a time {loop_ms:.1f} ms")
+    return dict(workload="batch256", instances=ninst, create_ms=create_ms,
+                persistent_ms=run_ms, instances_per_s=ninst / run_ms * 1e3,
+                latency_p50_ms=float(np.percentile(lat, 50)),
+                latency_p99_ms=float(np.percentile(lat, 99)),
+                loop_ms=loop_ms, loop_instances_per_s=ninst / loop_ms * 1e3,
+                loop_latency_p50_ms=float(np.percentile(done, 50)),
+                loop_latency_p99_ms=float(np.percentile(done, 99)),
+                speedup=loop_ms / run_ms)
+
+
 def measure_cpu(W, main, budget_s):
     import numpy as np
     import oracle
@@ -296,6 +352,7 @@ def main():
     ap.add_argument("--tile-k", type=int, default=0)
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (traffic-counter calibration)")
@@ -336,6 +393,7 @@ def main():
             traffic = None
     res["roofline"]["traffic"] = traffic
     grad = None if args.no_grad else measure_grad(P, W, torch, args)
+    batch = None if args.no_batch else measure_batch(P, W, torch, args)
     cpu = None if args.no_cpu else measure_cpu(W, res, args.cpu_budget)
     line = {
         "metric": METRIC,
@@ -357,6 +415,7 @@ def main():
         "qsu": res["qsu"],
         "evc": res["evc"],
         "grad": grad,
+        "batch": batch,
         "energy": res["energy"],
         "roofline": res["roofline"],
         "cpu_baseline": cpu,

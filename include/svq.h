@@ -189,6 +189,38 @@ svq_status sv_plan_paulis(int n, int g, const svq_pauli *terms, int n_terms, svq
                           int32_t *pass_out, uint64_t *local_out, int32_t *n_qr_out,
                           int32_t *n_pass_out);
 
+/* ---- batched VQE -------------------------------------------------------
+ * Many independent instances (each its own circuit, angles and Hamiltonian,
+ * qubit counts 10..26, all qubits local: no emulated global qubits, so no
+ * reordering) evaluated in one persistent kernel launch that is captured
+ * once in a HIP graph and replayed per call.  Every stage of an instance
+ * (psi0, each gate pass, each H|psi> pass, <psi|H psi>, each reverse adjoint
+ * pass, the final FP64 sums) is cut into 2^10-amplitude tiles; single-wave
+ * blocks pull (instance, stage, tile) items from one device queue and wait,
+ * with a bounded spin, for the instance's previous stage.
+ * The plans are built once (the schedule reused across VQE iterations,
+ * Section "Scheduling time"); only the angles change per call. */
+typedef struct svq_batch_s *svq_batch;
+
+/* gates[i][0..m[i]), theta of instance i has n_theta[i] entries, terms[i]
+ * [0..n_terms[i]), psi0[i] the initial basis state.  low_bits = 0 picks the
+ * tuned value.  The library allocates the state arena (two states per
+ * instance) and tables.  Errors: EINVAL (shapes, gates, masks), ENOMEM, EHIP. */
+svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *const *gates,
+                           const int32_t *m, const int32_t *n_theta,
+                           const svq_pauli *const *terms, const int32_t *n_terms,
+                           const uint64_t *psi0, int low_bits, void *stream, svq_batch *out);
+
+/* Run all instances for the given angles (theta[i] has n_theta[i] entries).
+ * energies_host[n_inst] and grads_host[sum n_theta] (concatenated in instance
+ * order) receive E and dE/dtheta; latency_ms_host[n_inst] (nullable) the
+ * time from kernel start to the completion of each instance (device clock).
+ * Synchronises the stream.  A dependency wait that exceeds its bound returns
+ * EHIP and poisons the batch. */
+svq_status sv_batch_run(svq_batch b, const double *const *theta, double *energies_host,
+                        double *grads_host, double *latency_ms_host);
+svq_status sv_batch_destroy(svq_batch b);
+
 /* Per-launch timing.  sv_profile(st, 1) clears the record and brackets every
  * later kernel launch of the handle with HIP events on its stream;
  * sv_profile(st, 0) stops recording.  sv_profile_read synchronises the stream

@@ -52,7 +52,8 @@ class SvqError(RuntimeError):
 EXPORTS = ("sv_create", "sv_destroy", "sv_set_basis", "sv_set_amplitudes", "sv_get_amplitudes",
            "sv_get_layout", "sv_device_ptr", "sv_apply_circuit", "sv_qr_permute",
            "sv_expectation", "sv_apply_hamiltonian", "sv_grad", "sv_plan_circuit",
-           "sv_plan_paulis", "sv_profile", "sv_profile_read", "sv_last_error")
+           "sv_plan_paulis", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
+           "sv_batch_destroy", "sv_last_error")
 
 
 def _load():
@@ -83,6 +84,12 @@ def _load():
     L.sv_plan_paulis.argtypes = [c_int, c_int, POINTER(svq_pauli), c_int, c_int, c_int,
                                  POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                  POINTER(c_uint64), POINTER(c_int32), POINTER(c_int32)]
+    L.sv_batch_create.argtypes = [c_int, POINTER(c_int32), POINTER(POINTER(svq_gate)),
+                                  POINTER(c_int32), POINTER(c_int32), POINTER(POINTER(svq_pauli)),
+                                  POINTER(c_int32), POINTER(c_uint64), c_int, vp, POINTER(vp)]
+    L.sv_batch_run.argtypes = [vp, POINTER(POINTER(c_double)), POINTER(c_double),
+                               POINTER(c_double), POINTER(c_double)]
+    L.sv_batch_destroy.argtypes = [vp]
     L.sv_profile.argtypes = [vp, c_int]
     L.sv_profile_read.argtypes = [vp, c_int, POINTER(c_int), POINTER(c_double)]
     L.sv_last_error.restype = ctypes.c_char_p
@@ -347,3 +354,58 @@ class State:
         th = circuit.theta if theta is None else theta
         return sv_grad(self.h, gates_array(circuit.gates), len(circuit.gates), th, len(th),
                        paulis_array(ham), len(ham.coef), sched)
+
+
+class Batch:
+    """Many VQE instances evaluated by one persistent, graph-captured launch
+    (sv_batch_create / sv_batch_run).  ``instances``: list of (circuit,
+    hamiltonian) pairs (workloads.Circuit / workloads.Hamiltonian)."""
+
+    def __init__(self, instances, low_bits=0, stream=None):
+        self.n = len(instances)
+        self._gates = [gates_array(c.gates) for c, _ in instances]
+        self._terms = [paulis_array(h) for _, h in instances]
+        self.n_theta = [c.n_params for c, _ in instances]
+        nq = (c_int32 * self.n)(*[c.n for c, _ in instances])
+        ms = (c_int32 * self.n)(*[len(c.gates) for c, _ in instances])
+        nth = (c_int32 * self.n)(*self.n_theta)
+        nts = (c_int32 * self.n)(*[len(h.coef) for _, h in instances])
+        psi0 = (c_uint64 * self.n)(*[c.psi0_index for c, _ in instances])
+        gp = (POINTER(svq_gate) * self.n)(*[ctypes.cast(g, POINTER(svq_gate)) for g in self._gates])
+        tp = (POINTER(svq_pauli) * self.n)(*[ctypes.cast(t, POINTER(svq_pauli)) for t in self._terms])
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream()
+            except ImportError:
+                stream = None
+        self.h = c_void_p()
+        _check(lib.sv_batch_create(self.n, nq, gp, ms, nth, tp, nts, psi0, low_bits,
+                                   _stream_ptr(stream), byref(self.h)))
+        self.theta0 = [np.ascontiguousarray(c.theta, dtype=np.float64) for c, _ in instances]
+
+    def run(self, thetas=None):
+        th = self.theta0 if thetas is None else [np.ascontiguousarray(t, dtype=np.float64)
+                                                 for t in thetas]
+        ptrs = (POINTER(c_double) * self.n)(*[_dptr(t) if t.size else None for t in th])
+        e = np.zeros(self.n)
+        g = np.zeros(max(1, sum(self.n_theta)))
+        lat = np.zeros(self.n)
+        _check(lib.sv_batch_run(self.h, ptrs, _dptr(e), _dptr(g), _dptr(lat)))
+        grads, o = [], 0
+        for k in self.n_theta:
+            grads.append(g[o:o + k].copy())
+            o += k
+        return e, grads, lat
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            _check(lib.sv_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

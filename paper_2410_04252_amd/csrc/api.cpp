@@ -912,3 +912,355 @@ svq_status sv_plan_paulis(int n, int g, const svq_pauli *terms, int n_terms, svq
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// batched VQE
+// ===========================================================================
+
+struct svq_batch_s {
+    int n_inst = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool poisoned = false;
+    std::vector<std::vector<GateN>> gates;
+    std::vector<int> ntheta;
+    std::vector<int> theta_off;            // offset of each instance in the grads output
+    std::vector<OpDesc> ops_fwd, ops_inv;  // filled per run
+    std::vector<int> op_gate, op_inst;     // gate index / instance of every op
+    std::vector<BatchInst> insts;
+    int nitems = 0, nstages = 0, total_theta = 0;
+    DevBuf arena, items, stages, dinsts, passes, hpasses, phases, d_ops_fwd, d_ops_inv, hgroups,
+        hterms, pptr, pgate, epart, gpart, energies, grads, counters, t_done, t_start;
+    OpDesc *h_ops_fwd = nullptr, *h_ops_inv = nullptr;   // pinned staging
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BatchArgs args;
+    ~svq_batch_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (h_ops_fwd) (void)hipHostFree(h_ops_fwd);
+        if (h_ops_inv) (void)hipHostFree(h_ops_inv);
+    }
+};
+
+namespace {
+
+svq_status batch_hip_fail(svq_batch b, hipError_t e, const char *what) {
+    if (b) b->poisoned = true;
+    return fail(SVQ_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define BHIPCHK(b, expr, what)                                  \
+    do {                                                        \
+        hipError_t _e = (expr);                                 \
+        if (_e != hipSuccess) return batch_hip_fail(b, _e, what); \
+    } while (0)
+
+template <typename T>
+hipError_t upload(DevBuf &d, const std::vector<T> &h, hipStream_t s) {
+    hipError_t e = d.ensure(std::max<size_t>(sizeof(T) * h.size(), 64));
+    if (e != hipSuccess || h.empty()) return e;
+    return hipMemcpyAsync(d.p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *const *gates,
+                           const int32_t *m, const int32_t *n_theta,
+                           const svq_pauli *const *terms, const int32_t *n_terms,
+                           const uint64_t *psi0, int low_bits, void *stream, svq_batch *out) {
+    if (!out) return fail(SVQ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_inst <= 0 || !n_qubits || !gates || !m || !n_theta || !terms || !n_terms || !psi0)
+        return fail(SVQ_EINVAL, "bad batch arguments");
+    const int K = kBatchK;
+    const int c = low_bits ? low_bits : env_int("SVQ_BATCH_LOW_BITS", 4);
+    if (c < 1 || c > 8) return fail(SVQ_EINVAL, "low_bits must be in [1, 8]");
+    // items per stage of an instance (each a contiguous tile range)
+    const int chunks = std::max(1, env_int("SVQ_BATCH_CHUNKS", 16));
+    auto b = std::make_unique<svq_batch_s>();
+    b->n_inst = n_inst;
+    b->stream = (hipStream_t)stream;
+    hipError_t he = hipGetDevice(&b->device);
+    if (he != hipSuccess) return fail(SVQ_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+    std::vector<BatchStage> stages;
+    std::vector<BatchPass> passes;
+    std::vector<BatchHPass> hpasses;
+    std::vector<PhaseDesc> phases;
+    std::vector<HpsiGroup> hgroups;
+    std::vector<HpsiTerm> hterms;
+    std::vector<int32_t> pptr, pgate;
+    int64_t arena_elems = 0;
+    int epart_total = 0, gpart_total = 0;
+    std::vector<int> inst_stage_count(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const int n = n_qubits[i];
+        if (n < K || n > 26) return fail(SVQ_EINVAL, "batch instances need 10 <= n <= 26");
+        if (m[i] < 0 || n_theta[i] < 0 || n_terms[i] < 1) return fail(SVQ_EINVAL, "bad instance sizes");
+        if (psi0[i] >> n) return fail(SVQ_EINVAL, "psi0 index >= 2^n");
+        std::vector<GateN> gn;
+        std::string err = normalize_gates(n, gates[i], m[i], n_theta[i], gn);
+        if (!err.empty()) return fail(SVQ_EINVAL, "instance " + std::to_string(i) + ": " + err);
+        std::vector<int> pos(n);
+        for (int q = 0; q < n; ++q) pos[q] = q;
+        CircuitPlan cp;
+        err = plan_circuit(n, 0, gn, SVQ_LAZY, K, gate_rb(K), c, pos, cp);
+        if (!err.empty()) return fail(SVQ_EINVAL, err);
+        PauliPlan pp;
+        err = plan_paulis(n, 0, terms[i], n_terms[i], SVQ_LAZY, K, c, false, pos, pp);
+        if (!err.empty()) return fail(SVQ_EINVAL, err);
+        if (cp.n_qr || pp.n_qr || !pp.wide_groups.empty() || cp.k != K || pp.k != K)
+            return fail(SVQ_EUNSUP, "instance " + std::to_string(i) + " needs a reorder or a wide term");
+        BatchInst I;
+        std::memset(&I, 0, sizeof(I));
+        I.n = n;
+        I.ntiles = 1 << (n - K);
+        I.nchunks = std::min(I.ntiles, chunks);
+        I.psi_off = arena_elems;
+        I.lam_off = arena_elems + (1LL << n);
+        arena_elems += 2LL << n;
+        I.psi0_lo = (uint32_t)psi0[i];
+        I.psi0_hi = (uint32_t)(psi0[i] >> 32);
+        I.epart_off = epart_total;
+        epart_total += I.nchunks;
+        I.m = m[i];
+        I.ntheta = n_theta[i];
+        I.gpart_off = gpart_total;
+        gpart_total += std::max(1, m[i]) * I.nchunks;
+        I.grad_off = b->total_theta;
+        b->theta_off.push_back(b->total_theta);
+        b->total_theta += n_theta[i];
+        // ops (fwd and inverse share layout), phases with global op offsets
+        const int op_base = (int)b->op_gate.size();
+        const int ph_base = (int)phases.size();
+        for (size_t o = 0; o < cp.ops.size(); ++o) {
+            b->ops_fwd.push_back(cp.ops[o]);
+            b->op_gate.push_back(cp.op_gate[o]);
+            b->op_inst.push_back(i);
+        }
+        for (PhaseDesc ph : cp.phases) {
+            ph.op0 += op_base;
+            phases.push_back(ph);
+        }
+        const int pass_base = (int)passes.size();
+        for (const PassArgs &pa : cp.passes) {
+            BatchPass bp;
+            std::memset(&bp, 0, sizeof(bp));
+            for (int j = 0; j < 16; ++j) bp.tphys[j] = pa.tphys[j];
+            bp.phase0 = pa.phase0 + ph_base;
+            bp.nphase = pa.nphase;
+            passes.push_back(bp);
+        }
+        const int hg_base = (int)hgroups.size(), ht_base = (int)hterms.size();
+        for (HpsiGroup hg : pp.hgroups) {
+            hg.t0 += ht_base;
+            hgroups.push_back(hg);
+        }
+        for (const HpsiTerm &ht : pp.hterms) hterms.push_back(ht);
+        const int hp_base = (int)hpasses.size();
+        for (const HpsiPassArgs &ha : pp.hpasses) {
+            BatchHPass bh;
+            std::memset(&bh, 0, sizeof(bh));
+            for (int j = 0; j < 16; ++j) bh.tphys[j] = ha.tphys[j];
+            bh.group0 = ha.group0 + hg_base;
+            bh.ngroups = ha.ngroups;
+            hpasses.push_back(bh);
+        }
+        // stages
+        I.stage0 = (int)stages.size();
+        auto add = [&](int type, int ntiles, int desc, int acc) {
+            BatchStage st;
+            st.type = type;
+            st.ntiles = ntiles;
+            st.desc = desc;
+            st.accumulate = acc;
+            stages.push_back(st);
+        };
+        add(IT_INIT, I.ntiles, 0, 0);
+        for (size_t p = 0; p < cp.passes.size(); ++p) add(IT_FWD, I.ntiles, pass_base + (int)p, 0);
+        for (size_t h = 0; h < pp.hpasses.size(); ++h) add(IT_HPSI, I.ntiles, hp_base + (int)h, h > 0);
+        add(IT_DOT, I.ntiles, 0, 0);
+        for (size_t p = cp.passes.size(); p-- > 0;) add(IT_ADJ, I.ntiles, pass_base + (int)p, 0);
+        add(IT_FINAL, 1, 0, 0);
+        I.nstages = (int)stages.size() - I.stage0;
+        inst_stage_count[i] = I.nstages;
+        // CSR parameter -> gates (gate indices local to the instance)
+        I.pptr_off = (int)pptr.size();
+        std::vector<std::vector<int>> byp(n_theta[i]);
+        for (int gi = 0; gi < m[i]; ++gi)
+            if (gn[gi].param >= 0 && (gn[gi].kind == SVQ_RX || gn[gi].kind == SVQ_RY || gn[gi].kind == SVQ_RZ ||
+                                      gn[gi].kind == SVQ_CPHASE || gn[gi].kind == SVQ_GIVENS))
+                byp[gn[gi].param].push_back(gi);
+        pptr.push_back((int)pgate.size());
+        for (int p = 0; p < n_theta[i]; ++p) {
+            for (int gi : byp[p]) pgate.push_back(gi);
+            pptr.push_back((int)pgate.size());
+        }
+        b->gates.push_back(std::move(gn));
+        b->ntheta.push_back(n_theta[i]);
+        b->insts.push_back(I);
+    }
+    b->nstages = (int)stages.size();
+    // items, stage-major
+    std::vector<BatchItem> items;
+    int maxst = 0;
+    for (int i = 0; i < n_inst; ++i) maxst = std::max(maxst, inst_stage_count[i]);
+    for (int sidx = 0; sidx < maxst; ++sidx)
+        for (int i = 0; i < n_inst; ++i) {
+            if (sidx >= inst_stage_count[i]) continue;
+            const BatchStage &st = stages[b->insts[i].stage0 + sidx];
+            const int nch = st.type == IT_FINAL ? 1 : b->insts[i].nchunks;
+            for (int ch = 0; ch < nch; ++ch) {
+                const int t0 = (int)((int64_t)st.ntiles * ch / nch);
+                const int t1 = (int)((int64_t)st.ntiles * (ch + 1) / nch);
+                BatchItem it;
+                std::memset(&it, 0, sizeof(it));
+                it.inst = i;
+                it.stage = sidx;
+                it.tile0 = t0;
+                it.ntile = t1 - t0;
+                it.chunk = ch;
+                items.push_back(it);
+            }
+        }
+    b->nitems = (int)items.size();
+    b->ops_inv = b->ops_fwd;
+    hipStream_t s = b->stream;
+    svq_batch bp = b.get();
+    BHIPCHK(bp, b->arena.ensure(sizeof(float2) * (size_t)arena_elems), "alloc arena");
+    BHIPCHK(bp, upload(b->items, items, s), "upload items");
+    BHIPCHK(bp, upload(b->stages, stages, s), "upload stages");
+    BHIPCHK(bp, upload(b->dinsts, b->insts, s), "upload instances");
+    BHIPCHK(bp, upload(b->passes, passes, s), "upload passes");
+    BHIPCHK(bp, upload(b->hpasses, hpasses, s), "upload H passes");
+    BHIPCHK(bp, upload(b->phases, phases, s), "upload phases");
+    BHIPCHK(bp, upload(b->hgroups, hgroups, s), "upload H groups");
+    BHIPCHK(bp, upload(b->hterms, hterms, s), "upload H terms");
+    BHIPCHK(bp, upload(b->pptr, pptr, s), "upload pptr");
+    BHIPCHK(bp, upload(b->pgate, pgate, s), "upload pgate");
+    BHIPCHK(bp, b->d_ops_fwd.ensure(sizeof(OpDesc) * std::max<size_t>(1, b->ops_fwd.size())), "alloc ops");
+    BHIPCHK(bp, b->d_ops_inv.ensure(sizeof(OpDesc) * std::max<size_t>(1, b->ops_fwd.size())), "alloc ops");
+    BHIPCHK(bp, b->epart.ensure(sizeof(double) * std::max(1, epart_total)), "alloc epart");
+    BHIPCHK(bp, b->gpart.ensure(sizeof(double) * std::max(1, gpart_total)), "alloc gpart");
+    BHIPCHK(bp, b->energies.ensure(sizeof(double) * n_inst), "alloc energies");
+    BHIPCHK(bp, b->grads.ensure(sizeof(double) * std::max(1, b->total_theta)), "alloc grads");
+    BHIPCHK(bp, b->counters.ensure(sizeof(int32_t) * (b->nstages + 2)), "alloc counters");
+    BHIPCHK(bp, b->t_done.ensure(sizeof(uint64_t) * n_inst), "alloc times");
+    BHIPCHK(bp, b->t_start.ensure(sizeof(uint64_t)), "alloc time");
+    BHIPCHK(bp, hipHostMalloc((void **)&b->h_ops_fwd, sizeof(OpDesc) * std::max<size_t>(1, b->ops_fwd.size())), "pinned ops");
+    BHIPCHK(bp, hipHostMalloc((void **)&b->h_ops_inv, sizeof(OpDesc) * std::max<size_t>(1, b->ops_fwd.size())), "pinned ops");
+    BHIPCHK(bp, hipStreamSynchronize(s), "sync");
+    BatchArgs &A = b->args;
+    std::memset(&A, 0, sizeof(A));
+    A.arena = (float2 *)b->arena.p;
+    A.items = (const BatchItem *)b->items.p;
+    A.stages = (const BatchStage *)b->stages.p;
+    A.insts = (const BatchInst *)b->dinsts.p;
+    A.passes = (const BatchPass *)b->passes.p;
+    A.hpasses = (const BatchHPass *)b->hpasses.p;
+    A.phases = (const PhaseDesc *)b->phases.p;
+    A.ops_fwd = (const OpDesc *)b->d_ops_fwd.p;
+    A.ops_inv = (const OpDesc *)b->d_ops_inv.p;
+    A.hgroups = (const HpsiGroup *)b->hgroups.p;
+    A.hterms = (const HpsiTerm *)b->hterms.p;
+    A.pptr = (const int32_t *)b->pptr.p;
+    A.pgate = (const int32_t *)b->pgate.p;
+    A.epart = (double *)b->epart.p;
+    A.gpart = (double *)b->gpart.p;
+    A.energies = (double *)b->energies.p;
+    A.grads = (double *)b->grads.p;
+    A.done = (int32_t *)b->counters.p;
+    A.head = (int32_t *)b->counters.p + b->nstages;
+    A.error = (int32_t *)b->counters.p + b->nstages + 1;
+    A.t_done = (uint64_t *)b->t_done.p;
+    A.t_start = (uint64_t *)b->t_start.p;
+    A.nitems = b->nitems;
+    A.spin_limit = env_int("SVQ_BATCH_SPIN_LIMIT", kBatchSpinLimit);
+    *out = b.release();
+    return SVQ_OK;
+}
+
+svq_status sv_batch_run(svq_batch b, const double *const *theta, double *energies_host,
+                        double *grads_host, double *latency_ms_host) {
+    if (!b) return fail(SVQ_EINVAL, "null batch");
+    if (b->poisoned) return fail(SVQ_EPOISONED, "batch poisoned by an earlier failure");
+    if (!theta || !energies_host || !grads_host) return fail(SVQ_EINVAL, "null argument");
+    BHIPCHK(b, hipSetDevice(b->device), "hipSetDevice");
+    for (int i = 0; i < b->n_inst; ++i) {
+        if (b->ntheta[i] && !theta[i]) return fail(SVQ_EINVAL, "theta[i] is NULL");
+        for (int p = 0; p < b->ntheta[i]; ++p)
+            if (!std::isfinite(theta[i][p])) return fail(SVQ_EINVAL, "non-finite theta");
+    }
+    // op coefficients for these angles, instance by instance
+    size_t o = 0;
+    for (int i = 0; i < b->n_inst; ++i) {
+        size_t o1 = o;
+        while (o1 < b->op_inst.size() && b->op_inst[o1] == i) ++o1;
+        std::vector<OpDesc> f(b->ops_fwd.begin() + o, b->ops_fwd.begin() + o1);
+        std::vector<int> og(b->op_gate.begin() + o, b->op_gate.begin() + o1);
+        std::vector<OpDesc> inv = f;
+        fill_ops(b->gates[i], theta[i], og, f, false);
+        fill_ops(b->gates[i], theta[i], og, inv, true);
+        for (size_t j = 0; j < inv.size(); ++j) {
+            const GateN &g = b->gates[i][og[j]];
+            inv[j].gslot = (g.param >= 0 && inv[j].gtype != GEN_NONE) ? og[j] : -1;
+            if (inv[j].gslot < 0) inv[j].gtype = GEN_NONE;
+        }
+        std::memcpy(b->h_ops_fwd + o, f.data(), sizeof(OpDesc) * f.size());
+        std::memcpy(b->h_ops_inv + o, inv.data(), sizeof(OpDesc) * inv.size());
+        o = o1;
+    }
+    const size_t nops = b->ops_fwd.size();
+    if (nops) {
+        BHIPCHK(b, hipMemcpyAsync(b->d_ops_fwd.p, b->h_ops_fwd, sizeof(OpDesc) * nops, hipMemcpyHostToDevice, b->stream), "upload ops");
+        BHIPCHK(b, hipMemcpyAsync(b->d_ops_inv.p, b->h_ops_inv, sizeof(OpDesc) * nops, hipMemcpyHostToDevice, b->stream), "upload ops");
+    }
+    if (!b->exec) {
+        // capture the counter reset and the persistent kernel once
+        hipStream_t cap;
+        BHIPCHK(b, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
+        BHIPCHK(b, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        int grid = 0;
+        hipError_t le = launch_batch(b->args, (int32_t *)b->counters.p, b->nstages + 2, cap, &grid);
+        hipError_t ce = hipStreamEndCapture(cap, &b->graph);
+        (void)hipStreamDestroy(cap);
+        BHIPCHK(b, le, "launch batch");
+        BHIPCHK(b, ce, "end capture");
+        BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "instantiate graph");
+    }
+    BHIPCHK(b, hipGraphLaunch(b->exec, b->stream), "graph launch");
+    int32_t err = 0;
+    BHIPCHK(b, hipMemcpyAsync(&err, (int32_t *)b->counters.p + b->nstages + 1, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream), "D2H");
+    BHIPCHK(b, hipMemcpyAsync(energies_host, b->energies.p, sizeof(double) * b->n_inst, hipMemcpyDeviceToHost, b->stream), "D2H");
+    if (b->total_theta)
+        BHIPCHK(b, hipMemcpyAsync(grads_host, b->grads.p, sizeof(double) * b->total_theta, hipMemcpyDeviceToHost, b->stream), "D2H");
+    std::vector<uint64_t> td(b->n_inst);
+    uint64_t t0 = 0;
+    BHIPCHK(b, hipMemcpyAsync(td.data(), b->t_done.p, sizeof(uint64_t) * b->n_inst, hipMemcpyDeviceToHost, b->stream), "D2H");
+    BHIPCHK(b, hipMemcpyAsync(&t0, b->t_start.p, sizeof(uint64_t), hipMemcpyDeviceToHost, b->stream), "D2H");
+    BHIPCHK(b, hipStreamSynchronize(b->stream), "sync");
+    if (err) {
+        b->poisoned = true;
+        return fail(SVQ_EHIP, "batch: a dependency wait exceeded its bound");
+    }
+    if (latency_ms_host) {
+        int khz = 100000;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device) != hipSuccess || khz <= 0)
+            khz = 100000;
+        for (int i = 0; i < b->n_inst; ++i)
+            latency_ms_host[i] = (double)(int64_t)(td[i] - t0) / (double)khz;
+    }
+    return SVQ_OK;
+}
+
+svq_status sv_batch_destroy(svq_batch b) {
+    if (!b) return fail(SVQ_EINVAL, "null batch");
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    delete b;
+    return SVQ_OK;
+}
+
+}  // extern "C"

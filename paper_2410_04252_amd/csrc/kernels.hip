@@ -16,7 +16,8 @@ template <> struct V2T<float> { using type = float2; };
 template <> struct V2T<double> { using type = double2; };
 
 // Insert a zero bit at each of the (ascending) positions pos[0..k-1].
-__device__ __forceinline__ uint64_t spread(uint64_t b, const int8_t *pos, int k) {
+template <typename TI>
+__device__ __forceinline__ uint64_t spread(uint64_t b, const TI *pos, int k) {
     for (int j = 0; j < k; ++j) {
         const int p = pos[j];
         const uint64_t lo = b & ((1ULL << p) - 1);
@@ -317,7 +318,8 @@ template <int RB, int K>
 struct RegMap {
     uint32_t ph[RB];    // physical offset of register bit b
     uint32_t sl[RB];    // LDS slot contribution of register bit b
-    __device__ __forceinline__ void init(const PhaseDesc &P, const int8_t *tphys) {
+    template <typename TI>
+    __device__ __forceinline__ void init(const PhaseDesc &P, const TI *tphys) {
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
             const int t = P.reg[b];
@@ -342,8 +344,8 @@ struct RegMap {
 };
 
 // Physical offset and LDS slot of the thread's own (lane, wave) bits.
-template <int NWB, int K>
-__device__ __forceinline__ void thread_maps(const PhaseDesc &P, const int8_t *tphys, uint32_t lane,
+template <int NWB, int K, typename TI>
+__device__ __forceinline__ void thread_maps(const PhaseDesc &P, const TI *tphys, uint32_t lane,
                                             uint32_t wave, uint32_t &tp, uint32_t &tslot) {
     uint32_t t = 0, p = 0;
 #pragma unroll
@@ -632,8 +634,8 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // Stage one tile into LDS: every thread issues all of its loads before the
 // first LDS write.  Thread bits are the tile's low bits (coalesced); the
 // offsets of the high part are uniform.
-template <typename V, int K, int TPB>
-__device__ __forceinline__ void stage_tile(V *lds, const V *__restrict__ src, const int8_t *tphys) {
+template <typename V, int K, int TPB, typename TI>
+__device__ __forceinline__ void stage_tile(V *lds, const V *__restrict__ src, const TI *tphys) {
     constexpr int NT = 1 << TPB;
     constexpr int E = 1 << (K - TPB);
     const uint32_t tid = threadIdx.x;
@@ -667,7 +669,7 @@ __global__ __launch_bounds__(1 << evc_tpb(K, sizeof(R) == 8)) void k_evc_pass(
     __shared__ V lds[TS];
     __shared__ double red[NT / 64];
     const uint64_t base = spread(blockIdx.x, a.tphys, K);
-    stage_tile<V, K, TPB>(lds, psi + base, a.tphys);
+    stage_tile<V, K, TPB, int8_t>(lds, psi + base, a.tphys);
     __syncthreads();
     double acc = 0.0;
     for (int gi = 0; gi < a.ngroups; ++gi) {
@@ -730,7 +732,7 @@ __global__ __launch_bounds__(1 << hpsi_tpb(K)) void k_hpsi_pass(
     constexpr int NQ = 1 << QH;
     __shared__ V lds[TS];
     const uint64_t base = spread(blockIdx.x, a.tphys, K);
-    stage_tile<V, K, TPB>(lds, psi + base, a.tphys);
+    stage_tile<V, K, TPB, int8_t>(lds, psi + base, a.tphys);
     __syncthreads();
     double lr[NQ], li[NQ];
 #pragma unroll
@@ -1181,6 +1183,290 @@ hipError_t launch_fill_basis(bool dbl, void *psi, uint64_t N, uint64_t idx, hipS
     const int g = grid_for(N);
     if (dbl) hipLaunchKernelGGL(k_fill_basis<double2>, dim3(g), dim3(256), 0, s, (double2 *)psi, N, idx);
     else hipLaunchKernelGGL(k_fill_basis<float2>, dim3(g), dim3(256), 0, s, (float2 *)psi, N, idx);
+    return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// batched persistent launch (complex64, 2^10-amplitude tiles, one wave/block)
+// ---------------------------------------------------------------------------
+
+namespace batch {
+
+constexpr int K = kBatchK;
+constexpr int RB = gate_rb(K);          // 4
+constexpr int NR = 1 << RB;             // 16 amplitudes per lane
+constexpr int HTPB = hpsi_tpb(K);       // 6
+constexpr int HQ = K - HTPB;            // 4
+constexpr int HNQ = 1 << HQ;
+static_assert((1 << (K - RB)) == 64, "one wave per tile");
+static_assert((1 << HTPB) == 64, "one wave per tile");
+
+__device__ __forceinline__ double wave_sum_d(double v) { return wave_sum(v); }
+
+template <bool ADJ>
+__device__ void gate_item(const BatchArgs &a, const BatchInst &N, const BatchPass &bp, uint32_t tile,
+                          float2 *lds, int chunk, bool first) {
+    using R = float;
+    using V = float2;
+    const uint32_t lane = threadIdx.x & 63u;
+    V *psi = a.arena + N.psi_off;
+    V *lam = a.arena + N.lam_off;
+    const OpDesc *ops = ADJ ? a.ops_inv : a.ops_fwd;
+    const int np = bp.nphase;
+    const PhaseDesc &P0 = a.phases[bp.phase0 + (ADJ ? np - 1 : 0)];
+    const PhaseDesc &PL = a.phases[bp.phase0 + (ADJ ? 0 : np - 1)];
+    const uint64_t base = spread(tile, bp.tphys, K);
+    uint32_t tp0, ts0, tpL, tsL;
+    thread_maps<0, K>(P0, bp.tphys, lane, 0u, tp0, ts0);
+    thread_maps<0, K>(PL, bp.tphys, lane, 0u, tpL, tsL);
+    (void)tsL;
+    RegMap<RB, K> m0, mL;
+    m0.init(P0, bp.tphys);
+    mL.init(PL, bp.tphys);
+    Regs<R, NR> v, w;
+    load_regs<V, R, NR, RB, K>(v, psi + base, tp0, m0);
+    if constexpr (ADJ) load_regs<V, R, NR, RB, K>(w, lam + base, tp0, m0);
+    uint32_t sw = ts0;
+    RegMap<RB, K> mc = m0;
+    for (int s = 0; s < np; ++s) {
+        const PhaseDesc &Pc = a.phases[bp.phase0 + (ADJ ? np - 1 - s : s)];
+        if (s > 0) {
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const uint32_t ad = sw ^ mc.slot(j);
+                lds[ad] = make_float2(v.re[j], v.im[j]);
+                if constexpr (ADJ) lds[(1 << K) + ad] = make_float2(w.re[j], w.im[j]);
+            }
+            __syncthreads();
+            uint32_t tpx;
+            thread_maps<0, K>(Pc, bp.tphys, lane, 0u, tpx, sw);
+            mc.init(Pc, bp.tphys);
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const uint32_t ad = sw ^ mc.slot(j);
+                const V e = lds[ad];
+                v.re[j] = e.x;
+                v.im[j] = e.y;
+                if constexpr (ADJ) {
+                    const V f = lds[(1 << K) + ad];
+                    w.re[j] = f.x;
+                    w.im[j] = f.y;
+                }
+            }
+            __syncthreads();
+        }
+        const int nop = Pc.nop;
+        const int op0 = Pc.op0;
+        for (int q = 0; q < nop; ++q) {
+            const OpDesc &o = ops[op0 + (ADJ ? nop - 1 - q : q)];
+            if constexpr (ADJ) {
+                if (o.gtype != GEN_NONE) {
+                    const double gv = wave_sum(op_gradient<R, NR, RB>(v, w, o));
+                    if (lane == 0) {
+                        double *slot = a.gpart + N.gpart_off + (size_t)o.gslot * N.nchunks + chunk;
+                        *slot = first ? gv : *slot + gv;   // this block owns the slot
+                    }
+                }
+                apply_op<R, NR, RB>(w, o);
+            }
+            apply_op<R, NR, RB>(v, o);
+        }
+    }
+    store_regs<V, R, NR, RB, K>(v, psi + base, tpL, mL);
+    if constexpr (ADJ) store_regs<V, R, NR, RB, K>(w, lam + base, tpL, mL);
+}
+
+__device__ void hpsi_item(const BatchArgs &a, const BatchInst &N, const BatchHPass &hp, int accumulate,
+                          uint32_t tile, float2 *lds) {
+    using R = float;
+    using V = float2;
+    const float2 *psi = a.arena + N.psi_off;
+    float2 *lam = a.arena + N.lam_off;
+    const uint64_t base = spread(tile, hp.tphys, K);
+    stage_tile<V, K, HTPB, int32_t>(lds, psi + base, hp.tphys);
+    __syncthreads();
+    double lr[HNQ], li[HNQ];
+#pragma unroll
+    for (int jj = 0; jj < HNQ; ++jj) lr[jj] = li[jj] = 0.0;
+    const uint32_t tid = threadIdx.x & 63u;
+    for (int gi = 0; gi < hp.ngroups; ++gi) {
+        const HpsiGroup &G = a.hgroups[hp.group0 + gi];
+        const uint32_t sthr = tid ^ G.xt;
+        R fr[HNQ], fi[HNQ];
+#pragma unroll
+        for (int jj = 0; jj < HNQ; ++jj) fr[jj] = fi[jj] = (R)0;
+        const int t1 = G.t0 + G.nt;
+        for (int ti = G.t0; ti < t1; ++ti) {
+            const HpsiTerm &T = a.hterms[ti];
+            const uint32_t zw = (uint32_t)__builtin_amdgcn_readfirstlane((int)T.zw) & (HNQ - 1);
+            const uint32_t par = (__builtin_popcount(sthr & T.zt) + __builtin_popcountll(base & T.zg)) & 1u;
+            const R ar = (R)T.are, ai = (R)T.aim;
+            fr[zw] += par ? -ar : ar;
+            fi[zw] += par ? -ai : ai;
+        }
+        wht<R, HNQ>(fr);
+        wht<R, HNQ>(fi);
+        const uint32_t xw = (uint32_t)__builtin_amdgcn_readfirstlane((int)G.xw);
+#pragma unroll
+        for (int jj = 0; jj < HNQ; ++jj) {
+            const uint32_t sc = (jj ^ xw) & (HNQ - 1);
+            const R f_r = fr[sc], f_i = fi[sc];
+            const V p = lds[sthr | (sc << HTPB)];
+            lr[jj] += (double)(f_r * p.x - f_i * p.y);
+            li[jj] += (double)(f_r * p.y + f_i * p.x);
+        }
+    }
+    uint32_t tpo = 0;
+#pragma unroll
+    for (int b = 0; b < HTPB; ++b) tpo |= ((tid >> b) & 1u) << hp.tphys[b];
+#pragma unroll
+    for (int jj = 0; jj < HNQ; ++jj) {
+        uint32_t hb = 0;
+#pragma unroll
+        for (int b = 0; b < HQ; ++b)
+            if ((jj >> b) & 1) hb |= 1u << hp.tphys[HTPB + b];
+        const uint64_t off = base + tpo + hb;
+        V o;
+        if (accumulate) {
+            const V prev = lam[off];
+            o.x = (R)((double)prev.x + lr[jj]);
+            o.y = (R)((double)prev.y + li[jj]);
+        } else {
+            o.x = (R)lr[jj];
+            o.y = (R)li[jj];
+        }
+        lam[off] = o;
+    }
+    __syncthreads();
+}
+
+// Contiguous tile t of an instance: element t * 2^K + j * 64 + lane.
+__device__ void init_item(const BatchArgs &a, const BatchInst &N, uint32_t tile) {
+    const uint32_t lane = threadIdx.x & 63u;
+    float2 *psi = a.arena + N.psi_off;
+    const uint64_t idx0 = ((uint64_t)N.psi0_hi << 32) | N.psi0_lo;
+#pragma unroll
+    for (int j = 0; j < (1 << K) / 64; ++j) {
+        const uint64_t e = ((uint64_t)tile << K) + (uint64_t)j * 64 + lane;
+        psi[e] = make_float2(e == idx0 ? 1.f : 0.f, 0.f);
+    }
+}
+
+__device__ double dot_tile(const BatchArgs &a, const BatchInst &N, uint32_t tile) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const float2 *psi = a.arena + N.psi_off;
+    const float2 *lam = a.arena + N.lam_off;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < (1 << K) / 64; ++j) {
+        const uint64_t e = ((uint64_t)tile << K) + (uint64_t)j * 64 + lane;
+        const float2 x = psi[e], y = lam[e];
+        acc += (double)x.x * y.x + (double)x.y * y.y;
+    }
+    return acc;
+}
+
+__device__ void final_item(const BatchArgs &a, const BatchInst &N, int inst) {
+    const uint32_t lane = threadIdx.x & 63u;
+    double e = 0.0;
+    for (int t = lane; t < N.nchunks; t += 64) e += a.epart[N.epart_off + t];
+    e = wave_sum(e);
+    if (lane == 0) a.energies[inst] = e;
+    for (int p = 0; p < N.ntheta; ++p) {
+        double g = 0.0;
+        const int e0 = a.pptr[N.pptr_off + p], e1 = a.pptr[N.pptr_off + p + 1];
+        for (int q = e0; q < e1; ++q) {
+            const double *src = a.gpart + N.gpart_off + (size_t)a.pgate[q] * N.nchunks;
+            for (int t = lane; t < N.nchunks; t += 64) g += src[t];
+        }
+        g = wave_sum(g);
+        if (lane == 0) a.grads[N.grad_off + p] = g;
+    }
+}
+
+}  // namespace batch
+
+// Persistent work-queue kernel.  Items are stored stage-major (all first
+// stages of every instance, then all second stages, ...), so every item a
+// block waits for was dequeued earlier by a running block; every wait is
+// bounded by spin_limit sleeps, after which the error flag is set and all
+// blocks drain.
+__global__ __launch_bounds__(64) void k_batch(const BatchArgs a) {
+    __shared__ float2 lds[2 << kBatchK];
+    const uint32_t lane = threadIdx.x & 63u;
+    if (blockIdx.x == 0 && lane == 0) *a.t_start = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = __hip_atomic_fetch_add(a.head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        it = __shfl(it, 0, 64);
+        if (it >= a.nitems) break;
+        int err = 0;
+        if (lane == 0) err = __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__shfl(err, 0, 64)) break;
+        const BatchItem I = a.items[it];
+        const BatchInst &N = a.insts[I.inst];
+        const int sidx = N.stage0 + I.stage;
+        const BatchStage S = a.stages[sidx];
+        if (I.stage > 0) {
+            const int need = a.stages[sidx - 1].ntiles;
+            int ok = 1;
+            if (lane == 0) {
+                // spin with relaxed loads (an acquire per iteration would
+                // invalidate this XCD's L2 under the working waves), then
+                // acquire once
+                int spins = 0;
+                while (__hip_atomic_load(a.done + sidx - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    __builtin_amdgcn_s_sleep(8);
+                    if (++spins > a.spin_limit) {
+                        __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = 0;
+                        break;
+                    }
+                }
+            }
+            if (!__shfl(ok, 0, 64)) break;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        double dacc = 0.0;
+        for (int k = 0; k < I.ntile; ++k) {
+            const uint32_t tile = (uint32_t)(I.tile0 + k);
+            switch (S.type) {
+            case IT_INIT: batch::init_item(a, N, tile); break;
+            case IT_FWD: batch::gate_item<false>(a, N, a.passes[S.desc], tile, lds, I.chunk, k == 0); break;
+            case IT_HPSI: batch::hpsi_item(a, N, a.hpasses[S.desc], S.accumulate, tile, lds); break;
+            case IT_DOT: dacc += batch::dot_tile(a, N, tile); break;
+            case IT_ADJ: batch::gate_item<true>(a, N, a.passes[S.desc], tile, lds, I.chunk, k == 0); break;
+            default: batch::final_item(a, N, I.inst); break;
+            }
+        }
+        if (S.type == IT_DOT) {
+            dacc = wave_sum(dacc);
+            if (lane == 0) a.epart[N.epart_off + I.chunk] = dacc;
+        }
+        if (lane == 0) {
+            __hip_atomic_fetch_add(a.done + sidx, I.ntile, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (S.type == IT_FINAL) a.t_done[I.inst] = __builtin_amdgcn_s_memrealtime();
+        }
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_batch(const BatchArgs &a, int32_t *counters, int ncounters, hipStream_t s,
+                        int *grid_out) {
+    // counters = [done..., head, error] in one array; a fill kernel (not a
+    // memset) resets them so the sequence can live in a captured graph
+    hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(256), 0, s, counters, ncounters, 0);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, 64, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 4;
+    const int grid = per_cu * num_cu();
+    if (grid_out) *grid_out = grid;
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -53,5 +53,8 @@ hipError_t launch_dot_re(bool dbl, const void *a, const void *b, uint64_t N, dou
 hipError_t launch_grad_reduce(const double *gpart, int nper, const int *pptr, const int *pgate,
                               int nparam, double *grad, hipStream_t s);
 hipError_t launch_fill_basis(bool dbl, void *psi, uint64_t N, uint64_t idx, hipStream_t s);
+// Reset counters (fill kernel) and launch the persistent batch kernel.
+hipError_t launch_batch(const BatchArgs &a, int32_t *counters, int ncounters, hipStream_t s,
+                        int *grid_out);
 
 }  // namespace svq

@@ -11,6 +11,8 @@
 // register bits, diagonal gates and controls act on any tile bit.  Between
 // phases the tile is transposed through LDS.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace svq {
@@ -135,6 +137,94 @@ struct HpsiPassArgs {
     int8_t tphys[16];
     int8_t tbits[16];     // thread-index bits (tile-local)
     int8_t wbits[8];      // cube bits (tile-local)
+};
+
+}  // namespace svq
+
+namespace svq {
+
+// ---------------------------------------------------------------------------
+// Batched persistent launch: many independent instances (g = 0, all qubits
+// local), every stage of every instance cut into tiles of 2^10 amplitudes,
+// processed by single-wave blocks that pull (instance, stage, tile) items from
+// one queue.  All descriptor fields are 32-bit (scalar loads).
+// ---------------------------------------------------------------------------
+
+constexpr int kBatchK = 10;          // tile bits of every batched stage
+constexpr int kBatchSpinLimit = 1 << 24;
+
+enum ItemType : int32_t {
+    IT_INIT = 0,    // write psi0 into the tile
+    IT_FWD = 1,     // forward gate pass
+    IT_HPSI = 2,    // lambda (+)= H psi, one pass
+    IT_DOT = 3,     // tile partial of Re <psi|lambda>
+    IT_ADJ = 4,     // reverse adjoint pass on psi and lambda
+    IT_FINAL = 5,   // energy and gradient of the instance
+};
+
+// One item: tiles [tile0, tile0 + ntile) of one stage, handled by one block,
+// which then publishes its completion once (one release per item, so the
+// number of cross-XCD cache write-backs stays small).
+struct BatchItem {
+    int32_t inst, stage, tile0, ntile;
+    int32_t chunk, pad[3];
+};
+
+struct BatchStage {
+    int32_t type;        // ItemType
+    int32_t ntiles;      // tiles of the stage
+    int32_t desc;        // gate pass or H pass index
+    int32_t accumulate;  // H pass: add into lambda
+};
+
+struct BatchPass {
+    int32_t tphys[16];   // physical bit of tile-local bit j
+    int32_t phase0, nphase;
+    int32_t pad[2];
+};
+
+struct BatchHPass {
+    int32_t tphys[16];
+    int32_t group0, ngroups;
+    int32_t pad[2];
+};
+
+struct BatchInst {
+    int32_t n, stage0, nstages, ntiles;
+    int32_t nchunks, pad0[3];     // items per stage (energy/gradient partial slots)
+    int64_t psi_off, lam_off;     // element offsets in the state arena
+    uint32_t psi0_lo, psi0_hi;    // initial basis state
+    int32_t epart_off, gpart_off; // energy partials (nchunks), gradient partials (m * nchunks)
+    int32_t m, ntheta;
+    int32_t pptr_off, pgate_off;  // CSR parameter -> gates
+    int32_t grad_off, pad;
+};
+
+struct BatchArgs {
+    float2 *arena;
+    const BatchItem *items;
+    const BatchStage *stages;
+    const BatchInst *insts;
+    const BatchPass *passes;
+    const BatchHPass *hpasses;
+    const PhaseDesc *phases;
+    const OpDesc *ops_fwd;
+    const OpDesc *ops_inv;
+    const HpsiGroup *hgroups;
+    const HpsiTerm *hterms;
+    const int32_t *pptr;
+    const int32_t *pgate;
+    double *epart;
+    double *gpart;
+    double *energies;
+    double *grads;
+    int32_t *done;            // per (instance, stage) completed tiles
+    int32_t *head;            // queue head
+    int32_t *error;           // set when a bounded wait expires
+    uint64_t *t_done;         // per instance: realtime clock at completion
+    uint64_t *t_start;        // realtime clock when the first block started
+    int32_t nitems;
+    int32_t spin_limit;
 };
 
 }  // namespace svq

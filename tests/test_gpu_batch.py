@@ -1,0 +1,92 @@
+"""Batched VQE (one persistent, graph-captured launch) against the oracle and
+against one-at-a-time evaluation."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tolerances import GRAD_REL, energy_ok
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    import paper_2410_04252_amd as P
+    torch.cuda.set_device(0)
+    return P
+
+
+def _instances(count, lo, hi, seed):
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed + i)
+        n = int(rng.integers(lo, hi + 1))
+        out.append((W.fabric(n, 6, seed + i), W.jw_terms(n, 60, seed + 500 + i)))
+    return out
+
+
+def test_batch_matches_oracle(P):
+    inst = _instances(10, 10, 13, 900)
+    print("batch vs oracle", flush=True)
+    b = P.Batch(inst)
+    e, grads, lat = b.run()
+    for i, (c, h) in enumerate(inst):
+        e_ref, g_ref = oracle.adjoint_grad(c, h)
+        ok, rel = energy_ok(e[i], e_ref, None, h, "c64")
+        assert ok, (i, rel)
+        assert np.linalg.norm(grads[i] - g_ref) <= GRAD_REL["c64"] * np.linalg.norm(g_ref), i
+    assert np.all(lat > 0)
+    # replay with other angles (the graph is reused, the op tables re-uploaded)
+    rng = np.random.default_rng(1)
+    thetas = [rng.uniform(-np.pi, np.pi, size=c.n_params) for c, _ in inst]
+    e2, grads2, _ = b.run(thetas)
+    for i, (c, h) in enumerate(inst):
+        c2 = W.Circuit(c.n, c.gates, thetas[i], c.psi0_index)
+        e_ref, g_ref = oracle.adjoint_grad(c2, h)
+        ok, rel = energy_ok(e2[i], e_ref, None, h, "c64")
+        assert ok, (i, rel)
+        assert np.linalg.norm(grads2[i] - g_ref) <= GRAD_REL["c64"] * np.linalg.norm(g_ref), i
+    b.close()
+
+
+def test_batch_equals_one_at_a_time(P):
+    inst = _instances(24, 10, 18, 1900)
+    print("batch vs single", flush=True)
+    b = P.Batch(inst)
+    e, grads, lat = b.run()
+    for i, (c, h) in enumerate(inst):
+        st = P.State(c.n, 0, "c64")
+        st.set_basis(c.psi0_index)
+        e1, g1, _ = st.grad(c, h)
+        st.close()
+        assert abs(e[i] - e1) <= 1e-6 * max(abs(e1), 1e-2 * np.abs(h.coef).sum()), i
+        assert np.linalg.norm(grads[i] - g1) <= 1e-5 * np.linalg.norm(g1), i
+    b.close()
+
+
+def test_batch_bounded_wait_expires_cleanly(P):
+    """A spin limit of zero (set from the host) makes every unmet dependency
+    wait give up at once: the kernel drains, the call reports EHIP and the
+    batch is poisoned, or, if no wait was ever unmet, the results are right."""
+    inst = _instances(16, 12, 16, 2900)
+    os.environ["SVQ_BATCH_SPIN_LIMIT"] = "0"
+    try:
+        b = P.Batch(inst)
+    finally:
+        del os.environ["SVQ_BATCH_SPIN_LIMIT"]
+    try:
+        e, grads, _ = b.run()
+    except P.SvqError as err:
+        assert err.status == -3
+        with pytest.raises(P.SvqError) as e2:
+            b.run()
+        assert e2.value.status == -6
+    else:
+        c, h = inst[0]
+        e_ref, _ = oracle.adjoint_grad(c, h)
+        assert energy_ok(e[0], e_ref, None, h, "c64")[0]
+    b.close()
