@@ -230,6 +230,19 @@ svq_status sv_batch_destroy(svq_batch b);
 svq_status sv_profile(svq_state st, int enable);
 svq_status sv_profile_read(svq_state st, int kind, int *count, double *total_ms);
 
+/* Host-only level-1 planning over arbitrary operators given by target masks
+ * (e.g. one 4-qubit GateFabric block per operator, the granularity of the
+ * paper's figures).  method: 0 ad hoc (eager), 1 flat tiling (Algs. 1-3),
+ * 2 hierarchical tiling (Algs. 4-5) with n_intra intra qubits; fill_highest
+ * selects Alg. 3's boundary fill (0: lowest free qubit, as the text says).
+ * order_out[m] = operator index per schedule position, local_out[m] = the
+ * local set M(g(x)) per position, intra_out[m] (hierarchical, nullable) the
+ * intra set per position; *n_qr_out counts changes of M (eq. n_qr) and
+ * *n_inter_out (hierarchical) the QRs that change the inter qubits. */
+svq_status sv_plan_ops(int n, int n_local, const uint64_t *targets, int m, int method,
+                       int n_intra, int fill_highest, int32_t *order_out, uint64_t *local_out,
+                       uint64_t *intra_out, int32_t *n_qr_out, int32_t *n_inter_out);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *sv_last_error(void);
 

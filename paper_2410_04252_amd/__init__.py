@@ -52,7 +52,7 @@ class SvqError(RuntimeError):
 EXPORTS = ("sv_create", "sv_destroy", "sv_set_basis", "sv_set_amplitudes", "sv_get_amplitudes",
            "sv_get_layout", "sv_device_ptr", "sv_apply_circuit", "sv_qr_permute",
            "sv_expectation", "sv_apply_hamiltonian", "sv_grad", "sv_plan_circuit",
-           "sv_plan_paulis", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
+           "sv_plan_paulis", "sv_plan_ops", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
            "sv_batch_destroy", "sv_last_error")
 
 
@@ -90,6 +90,9 @@ def _load():
     L.sv_batch_run.argtypes = [vp, POINTER(POINTER(c_double)), POINTER(c_double),
                                POINTER(c_double), POINTER(c_double)]
     L.sv_batch_destroy.argtypes = [vp]
+    L.sv_plan_ops.argtypes = [c_int, c_int, POINTER(c_uint64), c_int, c_int, c_int, c_int,
+                              POINTER(c_int32), POINTER(c_uint64), POINTER(c_uint64),
+                              POINTER(c_int32), POINTER(c_int32)]
     L.sv_profile.argtypes = [vp, c_int]
     L.sv_profile_read.argtypes = [vp, c_int, POINTER(c_int), POINTER(c_double)]
     L.sv_last_error.restype = ctypes.c_char_p
@@ -245,6 +248,23 @@ def sv_plan_circuit(n, g, gates, sched, tile_k=0):
                                byref(npass)))
     return dict(order=list(order)[:m], qr_tile=list(qt)[:m], pass_=list(ps)[:m],
                 local=list(loc)[:m], n_qr=nqr.value, n_pass=npass.value)
+
+
+PLAN_ADHOC, PLAN_FLAT, PLAN_HIERARCHICAL = 0, 1, 2
+
+
+def sv_plan_ops(n, n_local, targets, method, n_intra=0, fill_highest=False):
+    """Level-1 plan over operators given as qubit tuples (host only)."""
+    m = len(targets)
+    tm = (c_uint64 * max(1, m))(*[sum(1 << q for q in t) for t in targets])
+    order = (c_int32 * max(1, m))()
+    loc = (c_uint64 * max(1, m))()
+    intra = (c_uint64 * max(1, m))()
+    nqr, ninter = c_int32(), c_int32()
+    _check(lib.sv_plan_ops(n, n_local, tm, m, method, n_intra, int(fill_highest), order, loc,
+                           intra, byref(nqr), byref(ninter)))
+    return dict(order=list(order)[:m], local=list(loc)[:m], intra=list(intra)[:m],
+                n_qr=nqr.value, n_inter=ninter.value)
 
 
 def sv_plan_paulis(n, g, ham, sched, tile_k=0):

@@ -889,6 +889,44 @@ svq_status sv_plan_circuit(int n, int g, const svq_gate *gates, int m, svq_sched
     return SVQ_OK;
 }
 
+svq_status sv_plan_ops(int n, int n_local, const uint64_t *targets, int m, int method,
+                       int n_intra, int fill_highest, int32_t *order_out, uint64_t *local_out,
+                       uint64_t *intra_out, int32_t *n_qr_out, int32_t *n_inter_out) {
+    if (n < 1 || n > 64 || n_local < 1 || n_local > n || m < 0 || (m > 0 && !targets))
+        return fail(SVQ_EINVAL, "bad arguments");
+    if (method < 0 || method > 2) return fail(SVQ_EINVAL, "method must be 0, 1 or 2");
+    if (method == 2 && (n_intra < 0 || n_local + n_intra > n)) return fail(SVQ_EINVAL, "bad n_intra");
+    const uint64_t full = n >= 64 ? ~0ULL : ((1ULL << n) - 1);
+    std::vector<uint64_t> t(targets, targets + m);
+    for (uint64_t v : t)
+        if (!v || (v & ~full) || __builtin_popcountll(v) > n_local)
+            return fail(SVQ_EINVAL, "operator target set empty, out of range or wider than the local set");
+    std::vector<int> pos(n);
+    for (int q = 0; q < n; ++q) pos[q] = q;
+    std::vector<L1Tile> tiles;
+    std::vector<int> kinds;
+    std::vector<uint64_t> intra;
+    if (method == 0) tiles = ad_hoc(n, n_local, t, depth_order(t), pos);
+    else if (method == 1) tiles = flat_tiling(n, n_local, t, pos);
+    else tiles = hierarchical_tiling(n, n_local, n_intra, t, fill_highest != 0, kinds, intra);
+    int x = 0, nqr = 0, ninter = 0;
+    uint64_t prev = (1ULL << n_local) - 1;
+    for (size_t ti = 0; ti < tiles.size(); ++ti) {
+        if (tiles[ti].local != prev) ++nqr;
+        if (method == 2 && kinds[ti]) ++ninter;
+        prev = tiles[ti].local;
+        for (int op : tiles[ti].ops) {
+            if (order_out) order_out[x] = op;
+            if (local_out) local_out[x] = tiles[ti].local;
+            if (intra_out) intra_out[x] = method == 2 ? intra[ti] : 0;
+            ++x;
+        }
+    }
+    if (n_qr_out) *n_qr_out = nqr;
+    if (n_inter_out) *n_inter_out = ninter;
+    return SVQ_OK;
+}
+
 svq_status sv_plan_paulis(int n, int g, const svq_pauli *terms, int n_terms, svq_sched sched,
                           int tile_k, int32_t *order_out, int32_t *qr_tile_out, int32_t *pass_out,
                           uint64_t *local_out, int32_t *n_qr_out, int32_t *n_pass_out) {

@@ -150,6 +150,28 @@ static uint64_t qubit_mapping(uint64_t universe, uint64_t init, const std::vecto
     return QL;
 }
 
+// Alg. 3 with the boundary fill taking the highest free qubits instead.
+static uint64_t qubit_mapping_fill(uint64_t universe, const std::vector<int> &remain,
+                                   const std::vector<uint64_t> &targets, int budget, bool highest) {
+    uint64_t avail = universe;
+    uint64_t QL = 0;
+    for (int i : remain) {
+        uint64_t T = targets[i];
+        if ((T & ~avail) == 0 && popc(QL | T) <= budget) QL |= T;
+        else avail &= ~T;
+        if (!avail) break;
+    }
+    if (!QL) return 0;
+    if (!highest) {
+        for (uint64_t free = universe & ~QL; popc(QL) < budget && free; free &= free - 1)
+            QL |= free & (~free + 1);
+    } else {
+        for (int q = 63; q >= 0 && popc(QL) < budget; --q)
+            if (((universe >> q) & 1) && !((QL >> q) & 1)) QL |= bit(q);
+    }
+    return QL;
+}
+
 static uint64_t local_set(const std::vector<int> &pos, int nL) {
     uint64_t s = 0;
     for (size_t q = 0; q < pos.size(); ++q)
@@ -209,6 +231,66 @@ std::vector<L1Tile> flat_tiling(int n, int nL, const std::vector<uint64_t> &targ
             t.qr = tr;
             tiles.push_back(std::move(t));
         }
+    }
+    return tiles;
+}
+
+std::vector<L1Tile> hierarchical_tiling(int n, int nL, int n_intra,
+                                        const std::vector<uint64_t> &targets, bool fill_highest,
+                                        std::vector<int> &kinds, std::vector<uint64_t> &intra) {
+    const uint64_t Q = n >= 64 ? ~0ULL : (bit(n) - 1);
+    std::vector<int> remain = depth_order(targets);
+    uint64_t QL = bit(nL) - 1;
+    uint64_t QI = (bit(nL + n_intra) - 1) & ~QL;
+    std::vector<L1Tile> tiles;
+    kinds.clear();
+    intra.clear();
+    int pending_kind = 0;
+    bool first = true;
+    while (!remain.empty()) {
+        if (!first) {
+            // Alg. 5: intra-only pool first; valid only if it admits an operator
+            const uint64_t pool = QL | QI;
+            uint64_t nl = qubit_mapping_fill(pool, remain, targets, nL, fill_highest);
+            if (nl && !tile_construction(nl, remain, targets).empty()) {
+                QI = pool & ~nl;
+                QL = nl;
+                pending_kind = 0;
+            } else {
+                const uint64_t old_inter = Q & ~QL & ~QI;
+                nl = qubit_mapping_fill(Q, remain, targets, nL, fill_highest);
+                uint64_t qp = qubit_mapping_fill(Q, remain, targets, nL + n_intra, fill_highest);
+                uint64_t qi = qp & ~nl;
+                // keep |Q_intra| fixed when the two greedy picks diverge
+                if (!fill_highest) {
+                    for (int q = 0; q < n && popc(qi) < n_intra; ++q)
+                        if (!((nl >> q) & 1) && !((qi >> q) & 1)) qi |= bit(q);
+                    while (popc(qi) > n_intra) qi &= ~bit(63 - __builtin_clzll(qi));
+                } else {
+                    for (int q = n - 1; q >= 0 && popc(qi) < n_intra; --q)
+                        if (!((nl >> q) & 1) && !((qi >> q) & 1)) qi |= bit(q);
+                    while (popc(qi) > n_intra) qi &= qi - 1;
+                }
+                QL = nl;
+                QI = qi;
+                pending_kind = ((Q & ~QL & ~QI) == old_inter) ? 0 : 1;
+            }
+        }
+        first = false;
+        std::vector<int> G = tile_construction(QL, remain, targets);
+        if (G.empty()) continue;
+        std::vector<char> taken(targets.size(), 0);
+        for (int i : G) taken[i] = 1;
+        std::vector<int> rest;
+        for (int i : remain)
+            if (!taken[i]) rest.push_back(i);
+        remain.swap(rest);
+        L1Tile t;
+        t.local = QL;
+        t.ops = G;
+        tiles.push_back(std::move(t));
+        kinds.push_back(pending_kind);
+        intra.push_back(QI);
     }
     return tiles;
 }

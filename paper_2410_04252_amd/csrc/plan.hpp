@@ -61,6 +61,14 @@ std::vector<L1Tile> flat_tiling(int n, int nL, const std::vector<uint64_t> &targ
 std::vector<L1Tile> ad_hoc(int n, int nL, const std::vector<uint64_t> &targets,
                            const std::vector<int> &order, std::vector<int> &pos);
 
+// Hierarchical tiling, Algs. 4-5: local set plus n_intra intra qubits; a
+// remap first tries the intra-only pool Q_L u Q_intra (an intra QR) and
+// otherwise chooses from all qubits (an inter QR).  fill_highest selects the
+// boundary fill of Alg. 3.  kinds[t] = 1 for an inter QR before tile t.
+std::vector<L1Tile> hierarchical_tiling(int n, int nL, int n_intra,
+                                        const std::vector<uint64_t> &targets, bool fill_highest,
+                                        std::vector<int> &kinds, std::vector<uint64_t> &intra);
+
 // Alg. 6 over weighted supports (bit masks); ties prefer the current local
 // set, then the lexicographically first one.
 std::vector<L1Tile> tiling_pauli(int n, int nL, const std::vector<uint64_t> &supports,

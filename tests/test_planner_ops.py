@@ -1,0 +1,133 @@
+"""Level-1 planning over arbitrary operators (host only): the product's flat,
+ad hoc and hierarchical tilings against the paper's worked examples and the
+oracle, and the QR-count trend of the paper's evaluation."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import schedule as S
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2410_04252_amd as P
+    return P
+
+
+def _fig_ops():
+    ops = []
+    for _ in range(6):
+        ops += [tuple(range(4 * j, 4 * j + 4)) for j in range(4)]
+        ops += [tuple(range(4 * j + 2, 4 * j + 6)) for j in range(3)]
+    return ops
+
+
+def _mask(qs):
+    return sum(1 << q for q in qs)
+
+
+def test_flat_tiling_figure(P):
+    gold = json.load(open(os.path.join(GOLD, "flat_tiling_fig.json")))
+    ps = gold["paper_states"]
+    r = P.sv_plan_ops(gold["n"], gold["n_L"], _fig_ops(), P.PLAN_FLAT)
+    allm = (1 << gold["n"]) - 1
+    M = r["local"]
+    assert r["n_qr"] == ps["qr_count"]
+    a, b = ps["same_mapping_positions"]
+    assert M[a] == M[b]
+    i, j = ps["first_qr_between"]
+    assert M[i] != M[j]
+    assert [q for q in range(16) if (allm & ~M[j]) >> q & 1] == ps["global_after_first_qr"]
+    i, j = ps["second_qr_between"]
+    assert [q for q in range(16) if (allm & ~M[j]) >> q & 1] == ps["global_after_second_qr_reading"]
+
+
+def test_hierarchical_tiling_figure(P):
+    gold = json.load(open(os.path.join(GOLD, "hierarchical_tiling_fig.json")))
+    n = gold["n"]
+    r = P.sv_plan_ops(n, gold["n_L"], _fig_ops(), P.PLAN_HIERARCHICAL, gold["n_intra"],
+                      fill_highest=True)
+    events = []
+    allm = (1 << n) - 1
+    for x in range(1, len(r["order"])):
+        if (r["local"][x], r["intra"][x]) != (r["local"][x - 1], r["intra"][x - 1]):
+            inter_new = allm & ~r["local"][x] & ~r["intra"][x]
+            inter_old = allm & ~r["local"][x - 1] & ~r["intra"][x - 1]
+            events.append({"before": x, "kind": "intra" if inter_new == inter_old else "inter",
+                           "intra": [q for q in range(n) if r["intra"][x] >> q & 1],
+                           "inter": [q for q in range(n) if inter_new >> q & 1]})
+    assert events == gold["paper_states"]["events"]
+    assert r["n_inter"] == 2 and r["n_qr"] == 5
+
+
+@pytest.mark.parametrize("fill", [False, True])
+@pytest.mark.parametrize("seed", range(6))
+def test_hierarchical_matches_oracle(P, seed, fill):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(10, 17))
+    nL = n - int(rng.integers(3, 6))
+    n_intra = int(rng.integers(1, n - nL))
+    ops = [tuple(int(v) for v in rng.choice(n, size=int(rng.integers(1, 5)), replace=False))
+           for _ in range(int(rng.integers(20, 90)))]
+    order, M, tiles, events = S.hierarchical_tiling(n, ops, nL, n_intra,
+                                                    fill="highest" if fill else "lowest")
+    r = P.sv_plan_ops(n, nL, ops, P.PLAN_HIERARCHICAL, n_intra, fill_highest=fill)
+    assert r["order"] == order
+    assert r["local"] == [_mask(m) for m in M]
+    assert r["n_inter"] == sum(1 for e in events if e[1] == "inter")
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_flat_and_adhoc_ops_match_oracle(P, seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(8, 18))
+    nL = n - int(rng.integers(1, 5))
+    ops = [tuple(int(v) for v in rng.choice(n, size=int(rng.integers(1, 5)), replace=False))
+           for _ in range(int(rng.integers(10, 120)))]
+    order, M, _ = S.flat_tiling(n, ops, nL)
+    r = P.sv_plan_ops(n, nL, ops, P.PLAN_FLAT)
+    assert r["order"] == order and r["local"] == [_mask(m) for m in M]
+    assert r["n_qr"] == S.n_qr(M, nL)
+    order, M, _ = S.ad_hoc(n, ops, nL)
+    r = P.sv_plan_ops(n, nL, ops, P.PLAN_ADHOC)
+    assert r["order"] == order and r["local"] == [_mask(m) for m in M]
+
+
+def test_qr_count_sweep_block_level(P):
+    """GateFabric with 4n layers on 32 PEs (g = 5), one operator per 4-qubit
+    block as in the paper's evaluation: flat tiling needs fewer QRs as n grows
+    and far fewer than the ad hoc method, whose count grows with n."""
+    g = 5
+    flat, adhoc = {}, {}
+    for n in range(16, 37, 2):
+        ops = W.block_ops(n, 4 * n)
+        flat[n] = P.sv_plan_ops(n, n - g, ops, P.PLAN_FLAT)["n_qr"]
+        adhoc[n] = P.sv_plan_ops(n, n - g, ops, P.PLAN_ADHOC)["n_qr"]
+        if n <= 22:
+            _, M, _ = S.flat_tiling(n, ops, n - g)
+            _, M2, _ = S.ad_hoc(n, ops, n - g)
+            assert flat[n] == S.n_qr(M, n - g) and adhoc[n] == S.n_qr(M2, n - g)
+    ns = sorted(flat)
+    assert all(flat[a] >= flat[b] for a, b in zip(ns, ns[1:]))
+    assert all(adhoc[a] < adhoc[b] for a, b in zip(ns, ns[1:]))
+    ratio = [adhoc[n] / flat[n] for n in ns]
+    assert all(a < b for a, b in zip(ratio, ratio[1:]))
+    assert all(flat[n] < adhoc[n] for n in ns)
+
+
+def test_hierarchical_trades_inter_for_intra(P):
+    """Section 'Hierarchical tiling' (evaluation): with a two-level network the
+    hierarchical method has more QRs in total but fewer inter QRs than flat
+    tiling, all of whose QRs change inter qubits at these sizes."""
+    g, n_intra = 5, 3
+    for n in (24, 28, 30):
+        ops = W.block_ops(n, 4 * n)
+        fl = P.sv_plan_ops(n, n - g, ops, P.PLAN_FLAT)["n_qr"]
+        h = P.sv_plan_ops(n, n - g, ops, P.PLAN_HIERARCHICAL, n_intra, fill_highest=True)
+        assert h["n_qr"] >= fl
+        assert h["n_inter"] < fl
