@@ -158,6 +158,18 @@ svq_status sv_expectation(svq_state st, const svq_pauli *terms, int n_terms, svq
                           double *energy_host, double *energy_dev, double *chunk_dev,
                           svq_stats *stats);
 
+/* QSU-based EVC, the comparison method of Section "Evaluation" (EVC part):
+ * psi' = H|psi> is built by applying each Pauli string as a gate, in the
+ * terms' index order, with ad hoc reordering that makes the string's X/Y
+ * sites local (its Z sites are a diagonal phase and need no locality, as in
+ * eq. par_exp); both psi and psi' are permuted at every QR.  Then
+ * E = Re <psi|psi'> in FP64.  Each term costs one elementwise pass that reads
+ * psi and psi' and writes psi'.  A string with more X/Y sites than local
+ * qubits runs without a reorder.  Same outputs and errors as sv_expectation
+ * (no chunk sums); stats->n_qr counts the reorders. */
+svq_status sv_expectation_qsu(svq_state st, const svq_pauli *terms, int n_terms,
+                              double *energy_host, double *energy_dev, svq_stats *stats);
+
 /* H|psi> into a second handle of the same shape (out).  FP64 accumulation. */
 svq_status sv_apply_hamiltonian(svq_state st, const svq_pauli *terms, int n_terms,
                                 svq_state out);
@@ -221,20 +233,45 @@ svq_status sv_batch_run(svq_batch b, const double *const *theta, double *energie
                         double *grads_host, double *latency_ms_host);
 svq_status sv_batch_destroy(svq_batch b);
 
+/* ---- measured tuning ----------------------------------------------------
+ * The tile width k and the count c of forced low (coalescing) bits decide how
+ * many passes a circuit needs and how fast each pass streams.  These calls
+ * time candidate plans with HIP events on the handle's stream (one warm run,
+ * one timed run each), keep the fastest for the handle's size class
+ * (n, g, dtype) and use it whenever tile_k = 0 / low_bits = 0.  They overwrite
+ * the state.  k_out/c_out/ms_out (nullable) receive the winner. */
+svq_status sv_tune_circuit(svq_state st, const svq_gate *gates, int m, const double *theta,
+                           int n_theta, svq_sched sched, int *k_out, int *c_out, double *ms_out);
+svq_status sv_tune_paulis(svq_state st, const svq_pauli *terms, int n_terms, int *k_out,
+                          int *c_out, double *ms_out);
+/* Batch: tries items per stage (chunks) and low bits; arguments as
+ * sv_batch_create plus the angles; the winner is used by later
+ * sv_batch_create calls with low_bits = 0. */
+svq_status sv_batch_tune(int n_inst, const int32_t *n_qubits, const svq_gate *const *gates,
+                         const int32_t *m, const int32_t *n_theta, const svq_pauli *const *terms,
+                         const int32_t *n_terms, const uint64_t *psi0, const double *const *theta,
+                         void *stream, int *chunks_out, int *low_bits_out, double *ms_out);
+/* Persist / restore the tuned table (text: kind n g dtype k c ms per line). */
+svq_status sv_tune_save(const char *path);
+svq_status sv_tune_load(const char *path);
+
 /* Per-launch timing.  sv_profile(st, 1) clears the record and brackets every
  * later kernel launch of the handle with HIP events on its stream;
  * sv_profile(st, 0) stops recording.  sv_profile_read synchronises the stream
  * and returns the number of recorded launches of one kind and their summed
  * duration in ms.  Kinds: 0 gate pass, 1 QR pass, 2 EVC pass, 3 H|psi> pass,
- * 4 adjoint pass. */
+ * 4 adjoint pass, 5 Pauli-as-gate pass of the QSU-based EVC. */
 svq_status sv_profile(svq_state st, int enable);
 svq_status sv_profile_read(svq_state st, int kind, int *count, double *total_ms);
 
 /* Host-only level-1 planning over arbitrary operators given by target masks
  * (e.g. one 4-qubit GateFabric block per operator, the granularity of the
- * paper's figures).  method: 0 ad hoc (eager), 1 flat tiling (Algs. 1-3),
- * 2 hierarchical tiling (Algs. 4-5) with n_intra intra qubits; fill_highest
+ * paper's figures).  method: 0 ad hoc (eager) in breadth-first order,
+ * 1 flat tiling (Algs. 1-3), 2 hierarchical tiling (Algs. 4-5) with n_intra
+ * intra qubits, 3 ad hoc in the given order (the index order of the
+ * QSU-based EVC, a Pauli string's X/Y sites as targets); fill_highest
  * selects Alg. 3's boundary fill (0: lowest free qubit, as the text says).
+ * An empty target set (a diagonal string) is allowed and never moves qubits.
  * order_out[m] = operator index per schedule position, local_out[m] = the
  * local set M(g(x)) per position, intra_out[m] (hierarchical, nullable) the
  * intra set per position; *n_qr_out counts changes of M (eq. n_qr) and

@@ -51,8 +51,9 @@ class SvqError(RuntimeError):
 
 EXPORTS = ("sv_create", "sv_destroy", "sv_set_basis", "sv_set_amplitudes", "sv_get_amplitudes",
            "sv_get_layout", "sv_device_ptr", "sv_apply_circuit", "sv_qr_permute",
-           "sv_expectation", "sv_apply_hamiltonian", "sv_grad", "sv_plan_circuit",
-           "sv_plan_paulis", "sv_plan_ops", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
+           "sv_expectation", "sv_expectation_qsu", "sv_apply_hamiltonian", "sv_grad", "sv_plan_circuit",
+           "sv_plan_paulis", "sv_plan_ops", "sv_tune_circuit", "sv_tune_paulis",
+           "sv_batch_tune", "sv_tune_save", "sv_tune_load", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
            "sv_batch_destroy", "sv_last_error")
 
 
@@ -74,6 +75,8 @@ def _load():
     L.sv_qr_permute.argtypes = [vp, POINTER(c_int32)]
     L.sv_expectation.argtypes = [vp, POINTER(svq_pauli), c_int, c_int, POINTER(c_double),
                                  POINTER(c_double), POINTER(c_double), POINTER(svq_stats)]
+    L.sv_expectation_qsu.argtypes = [vp, POINTER(svq_pauli), c_int, POINTER(c_double),
+                                     POINTER(c_double), POINTER(svq_stats)]
     L.sv_apply_hamiltonian.argtypes = [vp, POINTER(svq_pauli), c_int, vp]
     L.sv_grad.argtypes = [vp, POINTER(svq_gate), c_int, POINTER(c_double), c_int,
                           POINTER(svq_pauli), c_int, c_int, POINTER(c_double), POINTER(c_double),
@@ -90,6 +93,16 @@ def _load():
     L.sv_batch_run.argtypes = [vp, POINTER(POINTER(c_double)), POINTER(c_double),
                                POINTER(c_double), POINTER(c_double)]
     L.sv_batch_destroy.argtypes = [vp]
+    ip = POINTER(c_int)
+    L.sv_tune_circuit.argtypes = [vp, POINTER(svq_gate), c_int, POINTER(c_double), c_int, c_int,
+                                  ip, ip, POINTER(c_double)]
+    L.sv_tune_paulis.argtypes = [vp, POINTER(svq_pauli), c_int, ip, ip, POINTER(c_double)]
+    L.sv_batch_tune.argtypes = [c_int, POINTER(c_int32), POINTER(POINTER(svq_gate)),
+                                POINTER(c_int32), POINTER(c_int32), POINTER(POINTER(svq_pauli)),
+                                POINTER(c_int32), POINTER(c_uint64), POINTER(POINTER(c_double)),
+                                vp, ip, ip, POINTER(c_double)]
+    L.sv_tune_save.argtypes = [ctypes.c_char_p]
+    L.sv_tune_load.argtypes = [ctypes.c_char_p]
     L.sv_plan_ops.argtypes = [c_int, c_int, POINTER(c_uint64), c_int, c_int, c_int, c_int,
                               POINTER(c_int32), POINTER(c_uint64), POINTER(c_uint64),
                               POINTER(c_int32), POINTER(c_int32)]
@@ -217,6 +230,15 @@ def sv_expectation(h, terms_c, n_terms, sched, energy_dev=None, chunk_dev=None, 
     return e.value, st
 
 
+def sv_expectation_qsu(h, terms_c, n_terms, energy_dev=None, want_host=True):
+    st = svq_stats()
+    e = c_double(0.0)
+    _check(lib.sv_expectation_qsu(h, terms_c, n_terms, byref(e) if want_host else None,
+                                  ctypes.cast(energy_dev, POINTER(c_double)) if energy_dev else None,
+                                  byref(st)))
+    return e.value, st
+
+
 def sv_apply_hamiltonian(h, terms_c, n_terms, out):
     _check(lib.sv_apply_hamiltonian(h, terms_c, n_terms, out))
 
@@ -250,7 +272,29 @@ def sv_plan_circuit(n, g, gates, sched, tile_k=0):
                 local=list(loc)[:m], n_qr=nqr.value, n_pass=npass.value)
 
 
-PLAN_ADHOC, PLAN_FLAT, PLAN_HIERARCHICAL = 0, 1, 2
+def sv_tune_circuit(h, gates_c, m, theta, n_theta, sched):
+    k, c, ms = c_int(), c_int(), c_double()
+    th = np.ascontiguousarray(theta, dtype=np.float64) if n_theta else np.zeros(1)
+    _check(lib.sv_tune_circuit(h, gates_c, m, _dptr(th), n_theta, sched, byref(k), byref(c),
+                               byref(ms)))
+    return k.value, c.value, ms.value
+
+
+def sv_tune_paulis(h, terms_c, n_terms):
+    k, c, ms = c_int(), c_int(), c_double()
+    _check(lib.sv_tune_paulis(h, terms_c, n_terms, byref(k), byref(c), byref(ms)))
+    return k.value, c.value, ms.value
+
+
+def sv_tune_save(path):
+    _check(lib.sv_tune_save(os.fsencode(path)))
+
+
+def sv_tune_load(path):
+    _check(lib.sv_tune_load(os.fsencode(path)))
+
+
+PLAN_ADHOC, PLAN_FLAT, PLAN_HIERARCHICAL, PLAN_ADHOC_INDEX = 0, 1, 2, 3
 
 
 def sv_plan_ops(n, n_local, targets, method, n_intra=0, fill_highest=False):
@@ -282,7 +326,7 @@ def sv_plan_paulis(n, g, ham, sched, tile_k=0):
                 local=list(loc)[:ng], n_qr=nqr.value, n_pass=npass.value)
 
 
-PROF_GATE, PROF_QR, PROF_EVC, PROF_HPSI, PROF_ADJ = 0, 1, 2, 3, 4
+PROF_GATE, PROF_QR, PROF_EVC, PROF_HPSI, PROF_ADJ, PROF_PAULI_GATE = 0, 1, 2, 3, 4, 5
 
 
 def sv_profile(h, enable):
@@ -370,6 +414,22 @@ class State:
     def expectation(self, ham, sched=LAZY):
         return sv_expectation(self.h, paulis_array(ham), len(ham.coef), sched)
 
+    def expectation_qsu(self, ham):
+        """The QSU-based comparison method (Pauli strings applied as gates)."""
+        return sv_expectation_qsu(self.h, paulis_array(ham), len(ham.coef))
+
+    def tune(self, circuit, theta=None, sched=LAZY):
+        """Time tile widths k and low-bit counts c on this circuit; the
+        fastest becomes the default for every state of this (n, g, dtype).
+        Overwrites the amplitudes."""
+        th = circuit.theta if theta is None else theta
+        return sv_tune_circuit(self.h, gates_array(circuit.gates), len(circuit.gates), th,
+                               len(th), sched)
+
+    def tune_paulis(self, ham):
+        """Same for the Pauli (EVC) passes; the state is read, not changed."""
+        return sv_tune_paulis(self.h, paulis_array(ham), len(ham.coef))
+
     def grad(self, circuit, ham, theta=None, sched=LAZY):
         th = circuit.theta if theta is None else theta
         return sv_grad(self.h, gates_array(circuit.gates), len(circuit.gates), th, len(th),
@@ -401,9 +461,23 @@ class Batch:
             except ImportError:
                 stream = None
         self.h = c_void_p()
+        self._args = (nq, gp, ms, nth, tp, nts, psi0)
+        self._stream = stream
         _check(lib.sv_batch_create(self.n, nq, gp, ms, nth, tp, nts, psi0, low_bits,
                                    _stream_ptr(stream), byref(self.h)))
         self.theta0 = [np.ascontiguousarray(c.theta, dtype=np.float64) for c, _ in instances]
+
+    def tune(self, thetas=None):
+        """Measured choice of items per stage and low bits for these
+        instances (used by later batches created with low_bits = 0)."""
+        th = self.theta0 if thetas is None else [np.ascontiguousarray(t, dtype=np.float64)
+                                                 for t in thetas]
+        ptrs = (POINTER(c_double) * self.n)(*[_dptr(t) if t.size else None for t in th])
+        ch, lb, ms = c_int(), c_int(), c_double()
+        nq, gp, mm, nth, tp, nts, psi0 = self._args
+        _check(lib.sv_batch_tune(self.n, nq, gp, mm, nth, tp, nts, psi0, ptrs,
+                                 _stream_ptr(self._stream), byref(ch), byref(lb), byref(ms)))
+        return ch.value, lb.value, ms.value
 
     def run(self, thetas=None):
         th = self.theta0 if thetas is None else [np.ascontiguousarray(t, dtype=np.float64)

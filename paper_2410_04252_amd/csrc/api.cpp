@@ -8,7 +8,9 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.hpp"
@@ -135,25 +137,68 @@ svq_status hip_fail(svq_state st, hipError_t e, const char *what) {
         if (_e != hipSuccess) return hip_fail(st, _e, what); \
     } while (0)
 
+// ---- tuned table: (kind, n, g, dtype) -> (k, c); kind 0 gate pass, 1 Pauli
+// pass, 2 batch (k = items per stage, c = low bits; n = g = 0) ----------------
+struct TuneKey {
+    int kind, n, g, dt;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(kind, n, g, dt) < std::tie(o.kind, o.n, o.g, o.dt);
+    }
+};
+struct TuneVal {
+    int k, c;
+    double ms;
+};
+std::map<TuneKey, TuneVal> &tune_table() {
+    static std::map<TuneKey, TuneVal> t;
+    return t;
+}
+std::mutex &tune_mutex() {
+    static std::mutex m;
+    return m;
+}
+bool tuned(int kind, int n, int g, int dt, TuneVal &out) {
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    auto it = tune_table().find({kind, n, g, dt});
+    if (it == tune_table().end()) return false;
+    out = it->second;
+    return true;
+}
+void set_tuned(int kind, int n, int g, int dt, TuneVal v) {
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    tune_table()[{kind, n, g, dt}] = v;
+}
+
+// Environment overrides win, then a measured value, then the default.
 int default_k(const svq_state_s *st) {
-    int k = env_int("SVQ_TILE_K", st->dbl() ? 12 : 12);
+    TuneVal tv;
+    int k = st->dbl() ? 12 : 12;
+    if (tuned(0, st->n, st->g, (int)st->dtype, tv)) k = tv.k;
+    k = env_int("SVQ_TILE_K", k);
     return std::max(8, std::min(13, std::min(k, st->n - st->g)));
 }
 
 int default_c(const svq_state_s *st) {
-    (void)st;
-    return env_int("SVQ_LOW_BITS", 4);
+    TuneVal tv;
+    int c = 4;
+    if (tuned(0, st->n, st->g, (int)st->dtype, tv)) c = tv.c;
+    return env_int("SVQ_LOW_BITS", c);
 }
 
 // Pauli passes are read-only: a wider tile covers more flip masks per read.
 int default_evc_k(const svq_state_s *st) {
-    int k = env_int("SVQ_EVC_K", st->dbl() ? 13 : 14);
+    TuneVal tv;
+    int k = st->dbl() ? 13 : 14;
+    if (tuned(1, st->n, st->g, (int)st->dtype, tv)) k = tv.k;
+    k = env_int("SVQ_EVC_K", k);
     return std::max(8, std::min(14, std::min(k, st->n - st->g)));
 }
 
 int default_evc_c(const svq_state_s *st) {
-    (void)st;
-    return env_int("SVQ_EVC_LOW_BITS", 4);
+    TuneVal tv;
+    int c = 4;
+    if (tuned(1, st->n, st->g, (int)st->dtype, tv)) c = tv.c;
+    return env_int("SVQ_EVC_LOW_BITS", c);
 }
 
 // Build the launch arguments of one QR step (disjoint transpositions).
@@ -894,13 +939,13 @@ svq_status sv_plan_ops(int n, int n_local, const uint64_t *targets, int m, int m
                        uint64_t *intra_out, int32_t *n_qr_out, int32_t *n_inter_out) {
     if (n < 1 || n > 64 || n_local < 1 || n_local > n || m < 0 || (m > 0 && !targets))
         return fail(SVQ_EINVAL, "bad arguments");
-    if (method < 0 || method > 2) return fail(SVQ_EINVAL, "method must be 0, 1 or 2");
+    if (method < 0 || method > 3) return fail(SVQ_EINVAL, "method must be 0, 1, 2 or 3");
     if (method == 2 && (n_intra < 0 || n_local + n_intra > n)) return fail(SVQ_EINVAL, "bad n_intra");
     const uint64_t full = n >= 64 ? ~0ULL : ((1ULL << n) - 1);
     std::vector<uint64_t> t(targets, targets + m);
     for (uint64_t v : t)
-        if (!v || (v & ~full) || __builtin_popcountll(v) > n_local)
-            return fail(SVQ_EINVAL, "operator target set empty, out of range or wider than the local set");
+        if ((v & ~full) || __builtin_popcountll(v) > n_local)
+            return fail(SVQ_EINVAL, "operator target set out of range or wider than the local set");
     std::vector<int> pos(n);
     for (int q = 0; q < n; ++q) pos[q] = q;
     std::vector<L1Tile> tiles;
@@ -908,6 +953,11 @@ svq_status sv_plan_ops(int n, int n_local, const uint64_t *targets, int m, int m
     std::vector<uint64_t> intra;
     if (method == 0) tiles = ad_hoc(n, n_local, t, depth_order(t), pos);
     else if (method == 1) tiles = flat_tiling(n, n_local, t, pos);
+    else if (method == 3) {
+        std::vector<int> ord(m);
+        for (int i = 0; i < m; ++i) ord[i] = i;
+        tiles = ad_hoc(n, n_local, t, ord, pos);
+    }
     else tiles = hierarchical_tiling(n, n_local, n_intra, t, fill_highest != 0, kinds, intra);
     int x = 0, nqr = 0, ninter = 0;
     uint64_t prev = (1ULL << n_local) - 1;
@@ -1014,10 +1064,12 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
     if (n_inst <= 0 || !n_qubits || !gates || !m || !n_theta || !terms || !n_terms || !psi0)
         return fail(SVQ_EINVAL, "bad batch arguments");
     const int K = kBatchK;
-    const int c = low_bits ? low_bits : env_int("SVQ_BATCH_LOW_BITS", 4);
+    TuneVal tv{64, 4, 0.0};
+    (void)tuned(2, 0, 0, 0, tv);
+    const int c = low_bits ? low_bits : env_int("SVQ_BATCH_LOW_BITS", tv.c);
     if (c < 1 || c > 8) return fail(SVQ_EINVAL, "low_bits must be in [1, 8]");
     // items per stage of an instance (each a contiguous tile range)
-    const int chunks = std::max(1, env_int("SVQ_BATCH_CHUNKS", 16));
+    const int chunks = std::max(1, env_int("SVQ_BATCH_CHUNKS", tv.k));
     auto b = std::make_unique<svq_batch_s>();
     b->n_inst = n_inst;
     b->stream = (hipStream_t)stream;
@@ -1298,6 +1350,264 @@ svq_status sv_batch_destroy(svq_batch b) {
     (void)hipSetDevice(b->device);
     (void)hipStreamSynchronize(b->stream);
     delete b;
+    return SVQ_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// measured tuning
+// ===========================================================================
+
+namespace {
+
+// Time one call of fn on the stream (events around the second of two runs).
+template <typename F>
+svq_status time_twice(hipStream_t s, F fn, double *ms) {
+    svq_status r = fn();
+    if (r) return r;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return fail(SVQ_EHIP, "event");
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return fail(SVQ_EHIP, "event");
+    }
+    (void)hipEventRecord(a, s);
+    r = fn();
+    (void)hipEventRecord(b, s);
+    float f = 0.f;
+    if (!r && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&f, a, b) != hipSuccess))
+        r = fail(SVQ_EHIP, "event timing");
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = f;
+    return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+svq_status sv_expectation_qsu(svq_state st, const svq_pauli *terms, int n_terms,
+                              double *energy_host, double *energy_dev, svq_stats *stats) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    if (n_terms < 0 || (n_terms > 0 && !terms)) return fail(SVQ_EINVAL, "bad term list");
+    const uint64_t full = st->n == 64 ? ~0ULL : ((1ULL << st->n) - 1);
+    for (int t = 0; t < n_terms; ++t) {
+        if ((terms[t].x & ~full) || (terms[t].z & ~full)) return fail(SVQ_EINVAL, "pauli mask beyond n qubits");
+        if (!std::isfinite(terms[t].coef)) return fail(SVQ_EINVAL, "non-finite coefficient");
+    }
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    HIPCHK(st, st->d_energy.ensure(sizeof(double)), "alloc energy");
+    double *edev = energy_dev ? energy_dev : (double *)st->d_energy.p;
+    const int nL = st->n - st->g;
+    // ad hoc plan over the full supports, index order
+    auto t0 = std::chrono::steady_clock::now();
+    std::vector<uint64_t> targets(n_terms);
+    std::vector<int> order(n_terms);
+    for (int t = 0; t < n_terms; ++t) {
+        targets[t] = __builtin_popcountll(terms[t].x) <= nL ? terms[t].x : 0;
+        order[t] = t;
+    }
+    std::vector<int> pos_end = st->pos;
+    std::vector<L1Tile> tiles = ad_hoc(st->n, nL, targets, order, pos_end);
+    // each term's masks in the layout it runs under
+    std::vector<WideTerm> wt(n_terms);
+    std::vector<int> cur = st->pos;
+    int nqr = 0;
+    for (const L1Tile &T : tiles) {
+        if (!T.qr.empty()) ++nqr;
+        for (const Transposition &tr : T.qr)
+            for (int q = 0; q < st->n; ++q) {
+                if (cur[q] == tr.a) cur[q] = tr.b;
+                else if (cur[q] == tr.b) cur[q] = tr.a;
+            }
+        for (int t : T.ops) {
+            WideTerm &w = wt[t];
+            std::memset(&w, 0, sizeof(w));
+            for (int q = 0; q < st->n; ++q) {
+                if ((terms[t].x >> q) & 1) w.x |= 1ULL << cur[q];
+                if ((terms[t].z >> q) & 1) w.z |= 1ULL << cur[q];
+            }
+            w.coef = terms[t].coef;
+            w.ny = __builtin_popcountll(terms[t].x & terms[t].z);
+        }
+    }
+    if (cur != pos_end) return fail(SVQ_EINVAL, "internal: ad hoc layout mismatch");
+    auto t1 = std::chrono::steady_clock::now();
+    if (n_terms == 0) {
+        HIPCHK(st, hipMemsetAsync(edev, 0, sizeof(double), st->stream), "zero energy");
+    } else {
+        HIPCHK(st, st->d_lam.ensure(st->bytes()), "alloc psi'");
+        DevBuf d_wt;
+        HIPCHK(st, d_wt.ensure(sizeof(WideTerm) * n_terms), "alloc terms");
+        HIPCHK(st, hipMemcpyAsync(d_wt.p, wt.data(), sizeof(WideTerm) * n_terms,
+                                  hipMemcpyHostToDevice, st->stream),
+               "upload terms");
+        double bytes = 0.0;
+        bool first = true;
+        for (const L1Tile &T : tiles) {
+            if (!T.qr.empty()) {
+                s = run_qr(st, st->buf, T.qr);
+                if (s) return s;
+                if (!first) {
+                    s = run_qr(st, st->d_lam.p, T.qr);
+                    if (s) return s;
+                }
+                bytes += qr_bytes(st, T.qr) * (first ? 1.0 : 2.0);
+            }
+            for (int t : T.ops) {
+                ProfScope ps(st, 5);
+                HIPCHK(st, launch_hpsi_direct(st->dbl(), st->buf, st->d_lam.p, st->N(),
+                                              (const WideTerm *)d_wt.p + t, 1, first ? 0 : 1,
+                                              st->stream),
+                       "pauli gate");
+                bytes += (first ? 2.0 : 3.0) * (double)st->bytes();
+                first = false;
+            }
+        }
+        const int dg = dot_grid(st->N());
+        HIPCHK(st, st->d_extra.ensure(sizeof(double) * dg), "alloc extra");
+        HIPCHK(st, launch_dot_re(st->dbl(), st->buf, st->d_lam.p, st->N(), (double *)st->d_extra.p,
+                                 st->stream),
+               "dot");
+        HIPCHK(st, launch_sum((const double *)st->d_extra.p, dg, edev, st->stream), "sum");
+        bytes += 2.0 * (double)st->bytes();
+        // d_wt is freed when it goes out of scope: finish its readers first
+        HIPCHK(st, hipStreamSynchronize(st->stream), "sync");
+        if (stats) stats->bytes = bytes;
+    }
+    st->pos = pos_end;
+    if (stats) {
+        stats->n_qr = nqr;
+        stats->n_evc_passes = n_terms;
+        stats->ms_plan = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    if (energy_host)
+        HIPCHK(st, hipMemcpyAsync(energy_host, edev, sizeof(double), hipMemcpyDeviceToHost, st->stream),
+               "copy energy");
+    if (energy_host) HIPCHK(st, hipStreamSynchronize(st->stream), "sync");
+    return SVQ_OK;
+}
+
+svq_status sv_tune_circuit(svq_state st, const svq_gate *gates, int m, const double *theta,
+                           int n_theta, svq_sched sched, int *k_out, int *c_out, double *ms_out) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    std::vector<GateN> gn;
+    std::string err = normalize_gates(st->n, gates, m, n_theta, gn);
+    if (!err.empty()) return fail(SVQ_EINVAL, err);
+    s = check_theta(gn, theta, n_theta);
+    if (s) return s;
+    const int nl = st->n - st->g;
+    TuneVal best{0, 0, 1e300};
+    for (int k = 10; k <= std::min(13, nl); ++k)
+        for (int c = 3; c <= 6; ++c) {
+            set_tuned(0, st->n, st->g, (int)st->dtype, {k, c, 0.0});
+            double ms = 0.0;
+            auto fn = [&]() -> svq_status {
+                svq_status r = sv_set_basis(st, 0);
+                if (r) return r;
+                return sv_apply_circuit(st, gates, m, theta, n_theta, sched, 0, nullptr);
+            };
+            s = time_twice(st->stream, fn, &ms);
+            if (s) return s;
+            if (ms < best.ms) best = {k, c, ms};
+        }
+    if (best.k == 0) return fail(SVQ_EUNSUP, "no tile width fits this state");
+    set_tuned(0, st->n, st->g, (int)st->dtype, best);
+    if (k_out) *k_out = best.k;
+    if (c_out) *c_out = best.c;
+    if (ms_out) *ms_out = best.ms;
+    return SVQ_OK;
+}
+
+svq_status sv_tune_paulis(svq_state st, const svq_pauli *terms, int n_terms, int *k_out,
+                          int *c_out, double *ms_out) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    const int nl = st->n - st->g;
+    TuneVal best{0, 0, 1e300};
+    for (int k = 11; k <= std::min(st->dbl() ? 13 : 14, nl); ++k)
+        for (int c = 3; c <= 6; ++c) {
+            set_tuned(1, st->n, st->g, (int)st->dtype, {k, c, 0.0});
+            double ms = 0.0;
+            auto fn = [&]() -> svq_status {
+                return sv_expectation(st, terms, n_terms, SVQ_LAZY, nullptr, nullptr, nullptr, nullptr);
+            };
+            s = time_twice(st->stream, fn, &ms);
+            if (s) return s;
+            if (ms < best.ms) best = {k, c, ms};
+        }
+    if (best.k == 0) return fail(SVQ_EUNSUP, "no tile width fits this state");
+    set_tuned(1, st->n, st->g, (int)st->dtype, best);
+    if (k_out) *k_out = best.k;
+    if (c_out) *c_out = best.c;
+    if (ms_out) *ms_out = best.ms;
+    return SVQ_OK;
+}
+
+svq_status sv_batch_tune(int n_inst, const int32_t *n_qubits, const svq_gate *const *gates,
+                         const int32_t *m, const int32_t *n_theta, const svq_pauli *const *terms,
+                         const int32_t *n_terms, const uint64_t *psi0, const double *const *theta,
+                         void *stream, int *chunks_out, int *low_bits_out, double *ms_out) {
+    if (n_inst <= 0 || !theta) return fail(SVQ_EINVAL, "bad arguments");
+    int total = 0;
+    for (int i = 0; i < n_inst; ++i) total += n_theta ? n_theta[i] : 0;
+    std::vector<double> e(n_inst), g(std::max(1, total));
+    TuneVal best{0, 0, 1e300};
+    const int chunk_c[] = {16, 32, 64, 128};
+    const int low_c[] = {3, 4, 5};
+    for (int ch : chunk_c)
+        for (int c : low_c) {
+            set_tuned(2, 0, 0, 0, {ch, c, 0.0});
+            svq_batch b = nullptr;
+            svq_status s = sv_batch_create(n_inst, n_qubits, gates, m, n_theta, terms, n_terms, psi0,
+                                           0, stream, &b);
+            if (s) return s;
+            s = sv_batch_run(b, theta, e.data(), g.data(), nullptr);
+            auto t0 = std::chrono::steady_clock::now();
+            if (!s) s = sv_batch_run(b, theta, e.data(), g.data(), nullptr);
+            auto t1 = std::chrono::steady_clock::now();
+            (void)sv_batch_destroy(b);
+            if (s) return s;
+            const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            if (ms < best.ms) best = {ch, c, ms};
+        }
+    set_tuned(2, 0, 0, 0, best);
+    if (chunks_out) *chunks_out = best.k;
+    if (low_bits_out) *low_bits_out = best.c;
+    if (ms_out) *ms_out = best.ms;
+    return SVQ_OK;
+}
+
+svq_status sv_tune_save(const char *path) {
+    if (!path) return fail(SVQ_EINVAL, "path is NULL");
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(SVQ_EINVAL, std::string("cannot write ") + path);
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    for (const auto &kv : tune_table())
+        std::fprintf(f, "%d %d %d %d %d %d %.6f\n", kv.first.kind, kv.first.n, kv.first.g,
+                     kv.first.dt, kv.second.k, kv.second.c, kv.second.ms);
+    std::fclose(f);
+    return SVQ_OK;
+}
+
+svq_status sv_tune_load(const char *path) {
+    if (!path) return fail(SVQ_EINVAL, "path is NULL");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(SVQ_EINVAL, std::string("cannot read ") + path);
+    int kind, n, g, dt, k, c;
+    double ms;
+    int cnt = 0;
+    while (std::fscanf(f, "%d %d %d %d %d %d %lf", &kind, &n, &g, &dt, &k, &c, &ms) == 7) {
+        if (kind < 0 || kind > 2 || k < 1 || c < 1) continue;
+        set_tuned(kind, n, g, dt, {k, c, ms});
+        ++cnt;
+    }
+    std::fclose(f);
+    (void)cnt;
     return SVQ_OK;
 }
 

@@ -131,3 +131,26 @@ def test_hierarchical_trades_inter_for_intra(P):
         h = P.sv_plan_ops(n, n - g, ops, P.PLAN_HIERARCHICAL, n_intra, fill_highest=True)
         assert h["n_qr"] >= fl
         assert h["n_inter"] < fl
+
+
+def test_evc_qr_sweep_alg6_vs_qsu_based(P):
+    """EVC (Section 'Evaluation', EVC part): Alg. 6 with diagonalization needs
+    far fewer QRs than the QSU-based method (index order, each Pauli string a
+    gate on its whole support, ad hoc reordering), and the gap widens with the
+    term count.  The QSU-based method makes each string's X/Y sites local (Z
+    sites are a diagonal phase); its index-order ad hoc plan equals the
+    oracle's."""
+    g = 5
+    ratios = []
+    for n, nt in ((20, 400), (24, 1000), (28, 2000), (30, 2000)):
+        ham = W.jw_terms(n, nt, 4000 + n)
+        sup = [tuple(q for q in range(n) if (int(x) >> q) & 1) for x in ham.x]
+        qsu = P.sv_plan_ops(n, n - g, sup, P.PLAN_ADHOC_INDEX)
+        lazy = P.sv_plan_paulis(n, g, ham, P.LAZY)["n_qr"]
+        if n <= 24:
+            order, M, qrs = S.ad_hoc(n, sup, n - g, order=list(range(len(sup))))
+            assert qsu["order"] == order and qsu["local"] == [_mask(m) for m in M]
+            assert qsu["n_qr"] == len(qrs)
+        assert lazy < qsu["n_qr"]
+        ratios.append(qsu["n_qr"] / max(1, lazy))
+    assert ratios[-1] > 20
