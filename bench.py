@@ -72,6 +72,12 @@ def measure_main(P, W, torch, args):
         return s1, s2
 
     log(f"[bench] workload {args.workload}: n={n} g={g} {dtype} gates={m} terms={nt}")
+    tuned = None
+    if args.tune:
+        kq, cq, msq = st.tune(circ)
+        ke, ce, mse = st.tune_paulis(ham)
+        tuned = dict(gate_k=kq, gate_c=cq, qsu_ms=msq, evc_k=ke, evc_c=ce, evc_ms=mse)
+        log(f"[bench] tuned: gate pass k={kq} c={cq} ({msq:.2f} ms), EVC k={ke} c={ce} ({mse:.2f} ms)")
     t0 = time.time()
     s1, s2 = step()          # plans are built (and cached) here
     torch.cuda.synchronize()
@@ -127,6 +133,7 @@ def measure_main(P, W, torch, args):
     evc_eager_ms = (time.perf_counter() - ta) * 1e3
     log(f"[bench] eager QSU {eager_ms:.2f} ms ({se.n_qr} QR, {se.n_gate_passes} passes); "
         f"eager EVC {evc_eager_ms:.2f} ms ({se2.n_qr} QR)")
+    qsu_evc = measure_qsu_evc(P, W, torch, st, ham, args) if args.qsu_terms > 0 else None
     st.close()
     out = dict(
         n=n, g=g, dtype=dtype, m=m, nt=nt, S=S, ms_step=ms_step, qsu_ms=qsu_ms, evc_ms=evc_ms,
@@ -141,12 +148,41 @@ def measure_main(P, W, torch, args):
                  groups=s2.n_groups, qr_lazy=s2.n_qr, qr_eager=se2.n_qr, eager_ms=evc_eager_ms,
                  evc_pass_avg_ms=t_ev / max(1, n_ev), plan_ms=s2.ms_plan,
                  read_gbs=s2.n_evc_passes * S / (max(1e-9, t_ev / max(1, args.steps)) * 1e-3) / 1e9),
+        qsu_evc=qsu_evc, tuned=tuned,
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
                       kernel="k_gate_pass<float,%d,4,false>" % (s1.tile_k or 12),
                       bytes_per_launch=gp_bytes, launches=n_gp, avg_ms=gp_avg_ms),
     )
     return out
+
+
+def measure_qsu_evc(P, W, torch, st, ham, args):
+    """The QSU-based comparison method on the first qsu_terms strings (index
+    order): each string applied as a gate into psi' (one elementwise pass per
+    string), ad hoc reorders, then one <psi|psi'>.  Its reorder count over all
+    strings comes from the planner."""
+    n, g = ham.n, st.g
+    k = min(args.qsu_terms, len(ham.coef))
+    sub = W.Hamiltonian(n, ham.x[:k], ham.z[:k], ham.coef[:k])
+    st.expectation_qsu(sub)                     # warm
+    torch.cuda.synchronize()
+    P.sv_profile(st.h, 1)
+    t0 = time.perf_counter()
+    _, sq = st.expectation_qsu(sub)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    npg, tpg = P.sv_profile_read(st.h, P.PROF_PAULI_GATE)
+    P.sv_profile(st.h, 0)
+    sup = [tuple(q for q in range(n) if (int(x) >> q) & 1) for x in ham.x]
+    nqr_all = P.sv_plan_ops(n, n - g, sup, P.PLAN_ADHOC_INDEX)["n_qr"]
+    S = (1 << n) * (8 if st.dtype == P.C64 else 16)
+    pg_avg = tpg / max(1, npg)
+    log(f"[bench] QSU-based EVC: {k} strings in {ms:.1f} ms ({k / ms * 1e3:.0f} terms/s), "
+        f"{sq.n_qr} QR; all {len(ham.coef)} strings need {nqr_all} QR")
+    return dict(terms_sampled=k, ms=ms, terms_per_s=k / (ms * 1e-3), qr_sample=sq.n_qr,
+                qr_all_terms=nqr_all, pauli_gate_avg_ms=pg_avg,
+                pauli_gate_gbs=3.0 * S / (pg_avg * 1e-3) / 1e9 if pg_avg > 0 else None)
 
 
 def measure_grad(P, W, torch, args):
@@ -227,6 +263,13 @@ def measure_batch(P, W, torch, args):
     ninst = len(inst)
     log(f"[bench] batch: {ninst} instances, n in [{min(c.n for c, _ in inst)}, "
         f"{max(c.n for c, _ in inst)}]")
+    tuned = None
+    if args.tune:
+        tb = P.Batch(inst)
+        ch, lb, tms = tb.tune()
+        tb.close()
+        tuned = dict(chunks=ch, low_bits=lb, ms=tms)
+        log(f"[bench] batch tuned: {ch} items per stage, {lb} low bits ({tms:.1f} ms)")
     t0 = time.perf_counter()
     b = P.Batch(inst)
     create_ms = (time.perf_counter() - t0) * 1e3
@@ -264,7 +307,7 @@ def measure_batch(P, W, torch, args):
     loop_ms = done[-1]
     log(f"[bench] batch {run_ms:.2f} ms ({ninst / run_ms * 1e3:.0f} inst/s, p50 {np.percentile(lat, 50):.2f} "
         f"p99 {np.percentile(lat, 99):.2f} ms); one at a time {loop_ms:.1f} ms")
-    return dict(workload="batch256", instances=ninst, create_ms=create_ms,
+    return dict(workload="batch256", instances=ninst, create_ms=create_ms, tuned=tuned,
                 persistent_ms=run_ms, instances_per_s=ninst / run_ms * 1e3,
                 latency_p50_ms=float(np.percentile(lat, 50)),
                 latency_p99_ms=float(np.percentile(lat, 99)),
@@ -354,6 +397,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--tune", action="store_true",
+                    help="run the measured tuner on the workload before timing")
+    ap.add_argument("--tune-save", default=None, help="write the tuned table to this file")
+    ap.add_argument("--qsu-terms", type=int, default=64,
+                    help="Pauli strings timed with the QSU-based comparison method (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (traffic-counter calibration)")
     ap.add_argument("--ingest-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
@@ -394,6 +442,8 @@ def main():
     res["roofline"]["traffic"] = traffic
     grad = None if args.no_grad else measure_grad(P, W, torch, args)
     batch = None if args.no_batch else measure_batch(P, W, torch, args)
+    if args.tune_save:
+        P.sv_tune_save(args.tune_save)
     cpu = None if args.no_cpu else measure_cpu(W, res, args.cpu_budget)
     line = {
         "metric": METRIC,
@@ -414,6 +464,8 @@ def main():
                    "hamiltonian": "Jordan-Wigner-like, coefficients N(0, 0.1)"},
         "qsu": res["qsu"],
         "evc": res["evc"],
+        "qsu_evc": res["qsu_evc"],
+        "tuned": res["tuned"],
         "grad": grad,
         "batch": batch,
         "energy": res["energy"],

@@ -503,3 +503,10 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# Measured tile widths / low-bit counts per size class, written by the tuner
+# (sv_tune_save) on an MI355X; SVQ_TUNE_FILE names another table, "" none.
+TUNE_FILE = os.environ.get("SVQ_TUNE_FILE", os.path.join(_HERE, "tuned_mi355x.txt"))
+if TUNE_FILE and os.path.exists(TUNE_FILE):
+    sv_tune_load(TUNE_FILE)

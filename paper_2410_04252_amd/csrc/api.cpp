@@ -191,7 +191,8 @@ int default_evc_k(const svq_state_s *st) {
     int k = st->dbl() ? 13 : 14;
     if (tuned(1, st->n, st->g, (int)st->dtype, tv)) k = tv.k;
     k = env_int("SVQ_EVC_K", k);
-    return std::max(8, std::min(14, std::min(k, st->n - st->g)));
+    // one staged tile must fit the 128 KiB the EVC pass reserves in LDS
+    return std::max(8, std::min(st->dbl() ? 13 : 14, std::min(k, st->n - st->g)));
 }
 
 int default_evc_c(const svq_state_s *st) {

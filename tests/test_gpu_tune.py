@@ -57,3 +57,27 @@ def test_tuned_batch_matches_oracle(P):
         assert ok, (i, rel)
         assert np.linalg.norm(grads[i] - g_ref) <= GRAD_REL["c64"] * np.linalg.norm(g_ref), i
     b.close()
+
+
+@pytest.mark.parametrize("k,c", [(10, 3), (11, 5), (12, 6), (13, 3), (13, 6)])
+def test_every_tuner_candidate_matches_oracle(P, k, c, monkeypatch):
+    """The candidates the tuner may pick (k in 10..13, c in 3..6 for gate
+    passes; k in 11..14 for Pauli passes) all give the oracle's results."""
+    circ = W.fabric(17, 10, 4040 + k)
+    ham = W.jw_terms(17, 250, 4050 + c)
+    ref = oracle.run_circuit(circ)
+    monkeypatch.setenv("SVQ_TILE_K", str(k))
+    monkeypatch.setenv("SVQ_LOW_BITS", str(c))
+    monkeypatch.setenv("SVQ_EVC_K", str(k + 1))
+    monkeypatch.setenv("SVQ_EVC_LOW_BITS", str(c))
+    print(f"tuner candidate k={k} c={c}", flush=True)
+    for dtype in ("c64", "c128"):
+        st = P.State(17, 3, dtype)
+        st.set_basis(circ.psi0_index)
+        stats = st.apply(circ)
+        assert stats.tile_k == k
+        assert np.abs(st.get_amplitudes() - ref).max() <= AMP[dtype]
+        e, _ = st.expectation(ham)
+        ok, rel = energy_ok(e, oracle.expectation(ref, ham), ref, ham, dtype)
+        assert ok, (dtype, rel)
+        st.close()
