@@ -11,10 +11,14 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsvq.so")
 SOURCES = ["kernels.hip", "plan.cpp", "api.cpp"]
 
-# Packed FP32 instructions are kept out of every HIP object.
+# Packed FP32 instructions are kept out of every HIP object.  Uniform
+# branches (the per-op dispatch of the gate pass: op codes come from scalar
+# loads) are left unstructurized, which keeps the register-resident amplitudes
+# in place across the dispatch instead of copying them at every merge.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+KERNEL_FLAGS = ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]
 
 
 def build(verbose: bool = False) -> str:
@@ -25,7 +29,7 @@ def build(verbose: bool = False) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        cmd = [hipcc] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc] + HIP_FLAGS + KERNEL_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd = [hipcc, "-x", "hip"] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
         procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT))

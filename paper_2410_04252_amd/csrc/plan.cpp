@@ -540,20 +540,50 @@ static void plan_phases(int k, int rb, const std::vector<L3Gate> &gs, CircuitPla
             phs.push_back({(uint32_t)regs, G});
         }
     }
+    // A load/store phase needs lanes on tile bits 0..3 (the c = 4 forced low
+    // physical bits: 16 lanes cover one 128-byte run); its registers may use
+    // any of the other bits.
     const uint32_t canon = canonical_regs(k, rb);
-    auto lanes_ok = [&](uint32_t regs) { return (regs & low6) == 0; };
+    const uint32_t low4 = 15u;
+    auto lanes_ok = [&](uint32_t regs) { return (regs & low4) == 0; };
     if (phs.empty() || !lanes_ok(phs.front().regs)) phs.insert(phs.begin(), Ph{canon, {}});
     if (!lanes_ok(phs.back().regs)) phs.push_back(Ph{canon, {}});
     for (auto &ph : phs) {
         PhaseDesc D;
         std::memset(&D, 0, sizeof(D));
         set_regs(ph.regs, rb, D);
-        if (lanes_ok(ph.regs)) {
+        if ((ph.regs & low6) == 0) {
             // keep lanes on bits 0..5 (coalesced global access)
             for (int i = 0; i < 6; ++i) D.lane[i] = i;
             int nw = 0;
             for (int b = 6; b < k; ++b)
                 if (!((ph.regs >> b) & 1)) D.wave[nw++] = b;
+        } else if (lanes_ok(ph.regs)) {
+            // lanes on bits 0..3 plus two free bits, preferring residues 4 and
+            // 5 mod 6 so that the LDS swizzle keeps the lanes on distinct banks
+            int lanes[6] = {0, 1, 2, 3, -1, -1};
+            uint32_t taken = ph.regs | low4;
+            for (int want = 4; want <= 5; ++want)
+                for (int b = 4; b < k; ++b)
+                    if (!((taken >> b) & 1) && b % 6 == want) {
+                        lanes[want] = b;
+                        taken |= 1u << b;
+                        break;
+                    }
+            for (int i = 4; i < 6; ++i)
+                if (lanes[i] < 0)
+                    for (int b = 4; b < k; ++b)
+                        if (!((taken >> b) & 1)) {
+                            lanes[i] = b;
+                            taken |= 1u << b;
+                            break;
+                        }
+            for (int i = 0; i < 8; ++i) D.lane[i] = 0;
+            for (int i = 0; i < 6; ++i) D.lane[i] = lanes[i];
+            int nw = 0;
+            for (int i = 0; i < 8; ++i) D.wave[i] = 0;
+            for (int b = 0; b < k; ++b)
+                if (!((taken >> b) & 1)) D.wave[nw++] = b;
         } else {
             assign_lanes(k, ph.regs, D);
         }
