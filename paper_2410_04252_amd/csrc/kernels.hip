@@ -74,27 +74,53 @@ __device__ __forceinline__ uint32_t tile_to_phys(uint32_t t, const int8_t *tphys
 
 // ---- gate ops on compile-time register bits -------------------------------
 
+// In-place rotation of (x, y) by the angle whose shear parameters are
+// (t, s): x' = cos(a) x - sin(a) y, y' = sin(a) x + cos(a) y.
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename R>
+__device__ __forceinline__ void shear_rot(R &x, R &y, R t, R s) {
+    x = fma_r(-t, y, x);
+    y = fma_r(s, x, y);
+    x = fma_r(-t, y, x);
+}
+
 template <int B, typename R, int NR>
 __device__ __forceinline__ void op_diag1(Regs<R, NR> &v, const OpDesc &o) {
-    const R d0r = (R)o.m[0], d0i = (R)o.m[1], d1r = (R)o.m[2], d1i = (R)o.m[3];
+    const R t0 = (R)o.m[16], s0 = (R)o.m[17], t1 = (R)o.m[18], s1 = (R)o.m[19];
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
-        const R dr = (j >> B) & 1 ? d1r : d0r, di = (j >> B) & 1 ? d1i : d0i;
-        const R xr = v.re[j], xi = v.im[j];
-        v.re[j] = xr * dr - xi * di;
-        v.im[j] = xr * di + xi * dr;
+        if ((j >> B) & 1) shear_rot(v.re[j], v.im[j], t1, s1);
+        else shear_rot(v.re[j], v.im[j], t0, s0);
+    }
+    if (o.flip & 1) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            if (!((j >> B) & 1)) { v.re[j] = -v.re[j]; v.im[j] = -v.im[j]; }
+    }
+    if (o.flip & 2) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            if ((j >> B) & 1) { v.re[j] = -v.re[j]; v.im[j] = -v.im[j]; }
     }
 }
 
 template <int B0, int B1, typename R, int NR>
 __device__ __forceinline__ void op_cphase(Regs<R, NR> &v, const OpDesc &o) {
-    const R dr = (R)o.m[2], di = (R)o.m[3];
+    const R t = (R)o.m[16], sn = (R)o.m[17];
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (!((j >> B0) & 1) || !((j >> B1) & 1)) continue;
-        const R xr = v.re[j], xi = v.im[j];
-        v.re[j] = xr * dr - xi * di;
-        v.im[j] = xr * di + xi * dr;
+        shear_rot(v.re[j], v.im[j], t, sn);
+    }
+    if (o.flip & 1) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            if (!((j >> B0) & 1) || !((j >> B1) & 1)) continue;
+            v.re[j] = -v.re[j];
+            v.im[j] = -v.im[j];
+        }
     }
 }
 
@@ -116,16 +142,20 @@ __device__ __forceinline__ void op_mix1(Regs<R, NR> &v, const OpDesc &o) {
 
 template <int B, typename R, int NR>
 __device__ __forceinline__ void op_roty(Regs<R, NR> &v, const OpDesc &o) {
-    const R cs = (R)o.m[0], sn = (R)o.m[1];
+    const R t = (R)o.m[16], sn = (R)o.m[17];
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j & (1 << B)) continue;
         const int j1 = j | (1 << B);
-        const R x0r = v.re[j], x0i = v.im[j], x1r = v.re[j1], x1i = v.im[j1];
-        v.re[j] = cs * x0r - sn * x1r;
-        v.im[j] = cs * x0i - sn * x1i;
-        v.re[j1] = sn * x0r + cs * x1r;
-        v.im[j1] = sn * x0i + cs * x1i;
+        shear_rot(v.re[j], v.re[j1], t, sn);
+        shear_rot(v.im[j], v.im[j1], t, sn);
+    }
+    if (o.flip & 1) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            v.re[j] = -v.re[j];
+            v.im[j] = -v.im[j];
+        }
     }
 }
 
@@ -159,17 +189,25 @@ __device__ __forceinline__ void op_cnot(Regs<R, NR> &v, const OpDesc &) {
 
 template <int B0, int B1, typename R, int NR>
 __device__ __forceinline__ void op_givens(Regs<R, NR> &v, const OpDesc &o) {
-    const R cs = (R)o.m[0], sn = (R)o.m[1];
+    const R t = (R)o.m[16], sn = (R)o.m[17];
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j & ((1 << B0) | (1 << B1))) continue;
         const int ju = j | (1 << B0);   // b0 = 1, b1 = 0
         const int jw = j | (1 << B1);   // b0 = 0, b1 = 1
-        const R ur = v.re[ju], ui = v.im[ju], wr = v.re[jw], wi = v.im[jw];
-        v.re[ju] = cs * ur - sn * wr;
-        v.im[ju] = cs * ui - sn * wi;
-        v.re[jw] = sn * ur + cs * wr;
-        v.im[jw] = sn * ui + cs * wi;
+        shear_rot(v.re[ju], v.re[jw], t, sn);
+        shear_rot(v.im[ju], v.im[jw], t, sn);
+    }
+    if (o.flip & 1) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            if (j & ((1 << B0) | (1 << B1))) continue;
+            const int ju = j | (1 << B0), jw = j | (1 << B1);
+            v.re[ju] = -v.re[ju];
+            v.im[ju] = -v.im[ju];
+            v.re[jw] = -v.re[jw];
+            v.im[jw] = -v.im[jw];
+        }
     }
 }
 
@@ -423,7 +461,9 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
         load_regs<V, R, NR, RB, K>(nv, psi + base, tp0, m0);
         if constexpr (ADJ) load_regs<V, R, NR, RB, K>(nw, lam + base, tp0, m0);
     }
-    for (; tile < ntiles; tile += (PERSIST ? gridDim.x : ntiles)) {
+    // One tile per block unless persistent: the loop then runs exactly once,
+    // which the compiler sees, so the load offsets die after the loads.
+    for (; tile < ntiles; tile += gridDim.x) {
         const uint64_t base = spread(tile, a.tphys, K);
         Regs<R, NR> v, w;
         if constexpr (PF) {
@@ -493,6 +533,7 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
         }
         store_regs<V, R, NR, RB, K>(v, psi + base, tpL, mL);
         if constexpr (ADJ) store_regs<V, R, NR, RB, K>(w, lam + base, tpL, mL);
+        if constexpr (!PERSIST) break;
     }
 }
 

@@ -598,8 +598,8 @@ static void plan_phases(int k, int rb, const std::vector<L3Gate> &gs, CircuitPla
             std::memset(&o, 0, sizeof(o));
             o.gslot = -1;
             o.type = op_type_of(g.kind);
-            o.cmask = 0;
-            o.pbit = -1;
+            o.spare = 0;
+            o.flip = 0;
             o.b0 = regpos[g.tq0];
             o.b1 = g.tq1 >= 0 ? regpos[g.tq1] : 0;
             P.ops.push_back(o);
@@ -715,6 +715,30 @@ static void set_c(double *m, int idx, double re, double im) {
     m[2 * idx + 1] = im;
 }
 
+// Shear parameters of the rotation with cosine c and sine s (see OpDesc).
+static void set_shear(OpDesc &o, int i, double c, double s) {
+    if (c < 0) {
+        c = -c;
+        s = -s;
+        o.flip |= 1 << i;
+    }
+    o.m[16 + 2 * i] = s / (1.0 + c);
+    o.m[17 + 2 * i] = s;
+}
+
+static void set_shears(OpDesc &o) {
+    o.flip = 0;
+    switch (o.type) {
+    case OP_GIVENS: case OP_ROTY: set_shear(o, 0, o.m[0], o.m[1]); break;
+    case OP_CPHASE: set_shear(o, 0, o.m[2], o.m[3]); break;
+    case OP_DIAG1:
+        set_shear(o, 0, o.m[0], o.m[1]);
+        set_shear(o, 1, o.m[2], o.m[3]);
+        break;
+    default: break;
+    }
+}
+
 void fill_ops(const std::vector<GateN> &gates, const double *theta, const std::vector<int> &op_gate,
               std::vector<OpDesc> &ops, bool inverse) {
     const double r2 = 1.0 / std::sqrt(2.0);
@@ -768,7 +792,10 @@ void fill_ops(const std::vector<GateN> &gates, const double *theta, const std::v
             break;
         }
         if (g.param < 0) o.gtype = GEN_NONE;
-        if (!inverse) continue;
+        if (!inverse) {
+            set_shears(o);
+            continue;
+        }
         switch (o.type) {   // U^dagger
         case OP_DIAG1: case OP_CPHASE:
             m[1] = -m[1];
@@ -791,6 +818,7 @@ void fill_ops(const std::vector<GateN> &gates, const double *theta, const std::v
         default:
             break;
         }
+        set_shears(o);
     }
 }
 

@@ -55,11 +55,17 @@ enum GenType : int32_t {
     GEN_CPHASE = 4,  // -|11><11| on (b0, b1)
 };
 
+// Unit-modulus ops (ROTY, GIVENS: a real rotation of an amplitude pair;
+// CPHASE, DIAG1: a phase, i.e. a rotation of (re, im)) run in place as three
+// shears, x += -t y; y += s x; x += -t y with t = tan(a/2), s = sin(a), which
+// needs no temporaries.  The angle is first reduced to |a| <= pi/2 (then
+// |t| <= 1) by writing R(a) = -R(a - pi); bit i of `flip` marks rotation i as
+// negated afterwards.  m[16 + 2i] = t_i, m[17 + 2i] = s_i.
 struct OpDesc {
     int32_t type;
     int32_t b0, b1;
-    int32_t pbit;
-    uint32_t cmask;
+    int32_t flip;
+    int32_t spare;
     int32_t gslot;   // adjoint: slot of this gate in the gradient partials (-1: none)
     int32_t gtype;   // GenType
     int32_t pad;
