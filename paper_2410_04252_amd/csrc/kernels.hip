@@ -402,18 +402,27 @@ __device__ __forceinline__ void thread_maps(const PhaseDesc &P, const TI *tphys,
     tslot = swz(t);
 }
 
-template <typename V, typename R, int NR, int RB, int K>
+// Tile loads and stores.  With OFF32 the in-tile byte offset fits 32 bits
+// (the tile's highest physical bit times the element size stays below 2^32),
+// so every access is a uniform base plus one 32-bit VGPR offset.
+template <typename V, typename R, int NR, int RB, int K, bool OFF32 = false>
 __device__ __forceinline__ void load_regs(Regs<R, NR> &v, const V *__restrict__ src, uint32_t tp,
                                           const RegMap<RB, K> &m) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
-        const V e = src[tp + m.phys(j)];
+        V e;
+        if constexpr (OFF32) {
+            const uint32_t off = (tp + m.phys(j)) * (uint32_t)sizeof(V);
+            e = *(const V *)((const char *)src + off);
+        } else {
+            e = src[tp + m.phys(j)];
+        }
         v.re[j] = e.x;
         v.im[j] = e.y;
     }
 }
 
-template <typename V, typename R, int NR, int RB, int K>
+template <typename V, typename R, int NR, int RB, int K, bool OFF32 = false>
 __device__ __forceinline__ void store_regs(const Regs<R, NR> &v, V *__restrict__ dst, uint32_t tp,
                                            const RegMap<RB, K> &m) {
 #pragma unroll
@@ -421,16 +430,21 @@ __device__ __forceinline__ void store_regs(const Regs<R, NR> &v, V *__restrict__
         V e;
         e.x = v.re[j];
         e.y = v.im[j];
-        dst[tp + m.phys(j)] = e;
+        if constexpr (OFF32) {
+            const uint32_t off = (tp + m.phys(j)) * (uint32_t)sizeof(V);
+            *(V *)((char *)dst + off) = e;
+        } else {
+            dst[tp + m.phys(j)] = e;
+        }
     }
 }
 
 // One gate pass (forward), or one reverse adjoint pass when ADJ: psi and
 // lam both get U^dagger of every op in reverse order, and each parametric op
-// first records 2 Im <lam|K|psi> per wave into gpart.  The grid is
-// persistent: a block walks tiles tile = blockIdx.x, +gridDim.x, ... and
-// prefetches the next tile into registers while it works on the current one.
-template <typename R, int K, int RB, bool ADJ, bool PERSIST>
+// first records 2 Im <lam|K|psi> per wave into gpart.  One block per tile:
+// load with the first phase's mapping, run the phases (an LDS transpose
+// between consecutive ones), store with the last phase's mapping.
+template <typename R, int K, int RB, bool ADJ, bool OFF32>
 __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
     typename V2T<R>::type *__restrict__ psi, typename V2T<R>::type *__restrict__ lam,
     const PassArgs a, const PhaseDesc *__restrict__ phases, const OpDesc *__restrict__ ops,
@@ -440,101 +454,81 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
     constexpr int NT = 1 << (K - RB);
     constexpr int NW = NT / 64;
     constexpr int NWB = K - RB - 6;
-    // register prefetch of the next tile (persistent grid only)
-    constexpr bool PF = PERSIST && !(ADJ && sizeof(R) == 8);
     __shared__ V lds[(ADJ ? 2 : 1) << K];
+    const uint32_t tile = blockIdx.x;
+    if (tile >= ntiles) return;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const int np = a.nphase;
     const PhaseDesc &P0 = phases[a.phase0 + (ADJ ? np - 1 : 0)];   // load mapping
     const PhaseDesc &PL = phases[a.phase0 + (ADJ ? 0 : np - 1)];   // store mapping
-    uint32_t tp0, ts0, tpL, tsL;
-    thread_maps<NWB, K>(P0, a.tphys, lane, wave, tp0, ts0);
+    const uint64_t base = spread(tile, a.tphys, K);
+    Regs<R, NR> v, w;
+    uint32_t sw;
+    RegMap<RB, K> mc;
+    {
+        uint32_t tp0;
+        thread_maps<NWB, K>(P0, a.tphys, lane, wave, tp0, sw);
+        mc.init(P0, a.tphys);
+        load_regs<V, R, NR, RB, K, OFF32>(v, psi + base, tp0, mc);
+        if constexpr (ADJ) load_regs<V, R, NR, RB, K, OFF32>(w, lam + base, tp0, mc);
+    }
+    for (int s = 0; s < np; ++s) {
+        const PhaseDesc &Pc = phases[a.phase0 + (ADJ ? np - 1 - s : s)];
+        if (s > 0) {
+            // transpose through LDS: write with the old mapping, read with the new
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const uint32_t ad = sw ^ mc.slot(j);
+                V e;
+                e.x = v.re[j];
+                e.y = v.im[j];
+                lds[ad] = e;
+                if constexpr (ADJ) {
+                    V f;
+                    f.x = w.re[j];
+                    f.y = w.im[j];
+                    lds[(1 << K) + ad] = f;
+                }
+            }
+            __syncthreads();
+            uint32_t tpx;
+            thread_maps<NWB, K>(Pc, a.tphys, lane, wave, tpx, sw);
+            mc.init(Pc, a.tphys);
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const uint32_t ad = sw ^ mc.slot(j);
+                const V e = lds[ad];
+                v.re[j] = e.x;
+                v.im[j] = e.y;
+                if constexpr (ADJ) {
+                    const V f = lds[(1 << K) + ad];
+                    w.re[j] = f.x;
+                    w.im[j] = f.y;
+                }
+            }
+        }
+        const int nop = Pc.nop;
+        const int op0 = Pc.op0;
+        for (int q = 0; q < nop; ++q) {
+            const OpDesc &o = ops[op0 + (ADJ ? nop - 1 - q : q)];
+            if constexpr (ADJ) {
+                if (o.gtype != GEN_NONE) {
+                    const double gv = wave_sum(op_gradient<R, NR, RB>(v, w, o));
+                    if (lane == 0) gpart[((size_t)o.gslot * ntiles + tile) * NW + wave] = gv;
+                }
+                apply_op<R, NR, RB>(w, o);
+            }
+            apply_op<R, NR, RB>(v, o);
+        }
+    }
+    uint32_t tpL, tsL;
     thread_maps<NWB, K>(PL, a.tphys, lane, wave, tpL, tsL);
     (void)tsL;
-    RegMap<RB, K> m0, mL;
-    m0.init(P0, a.tphys);
+    RegMap<RB, K> mL;
     mL.init(PL, a.tphys);
-    uint32_t tile = blockIdx.x;
-    Regs<R, NR> nv, nw;
-    if (PF && tile < ntiles) {
-        const uint64_t base = spread(tile, a.tphys, K);
-        load_regs<V, R, NR, RB, K>(nv, psi + base, tp0, m0);
-        if constexpr (ADJ) load_regs<V, R, NR, RB, K>(nw, lam + base, tp0, m0);
-    }
-    // One tile per block unless persistent: the loop then runs exactly once,
-    // which the compiler sees, so the load offsets die after the loads.
-    for (; tile < ntiles; tile += gridDim.x) {
-        const uint64_t base = spread(tile, a.tphys, K);
-        Regs<R, NR> v, w;
-        if constexpr (PF) {
-            v = nv;
-            if constexpr (ADJ) w = nw;
-            const uint32_t nt = tile + gridDim.x;
-            if (nt < ntiles) {
-                const uint64_t nbase = spread(nt, a.tphys, K);
-                load_regs<V, R, NR, RB, K>(nv, psi + nbase, tp0, m0);
-                if constexpr (ADJ) load_regs<V, R, NR, RB, K>(nw, lam + nbase, tp0, m0);
-            }
-        } else {
-            load_regs<V, R, NR, RB, K>(v, psi + base, tp0, m0);
-            if constexpr (ADJ) load_regs<V, R, NR, RB, K>(w, lam + base, tp0, m0);
-        }
-        uint32_t sw = ts0;
-        RegMap<RB, K> mc = m0;
-        for (int s = 0; s < np; ++s) {
-            const PhaseDesc &Pc = phases[a.phase0 + (ADJ ? np - 1 - s : s)];
-            if (s > 0) {
-                // transpose through LDS: write with the old mapping, read with the new
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < NR; ++j) {
-                    const uint32_t ad = sw ^ mc.slot(j);
-                    V e;
-                    e.x = v.re[j];
-                    e.y = v.im[j];
-                    lds[ad] = e;
-                    if constexpr (ADJ) {
-                        V f;
-                        f.x = w.re[j];
-                        f.y = w.im[j];
-                        lds[(1 << K) + ad] = f;
-                    }
-                }
-                __syncthreads();
-                uint32_t tpx;
-                thread_maps<NWB, K>(Pc, a.tphys, lane, wave, tpx, sw);
-                mc.init(Pc, a.tphys);
-#pragma unroll
-                for (int j = 0; j < NR; ++j) {
-                    const uint32_t ad = sw ^ mc.slot(j);
-                    const V e = lds[ad];
-                    v.re[j] = e.x;
-                    v.im[j] = e.y;
-                    if constexpr (ADJ) {
-                        const V f = lds[(1 << K) + ad];
-                        w.re[j] = f.x;
-                        w.im[j] = f.y;
-                    }
-                }
-            }
-            const int nop = Pc.nop;
-            const int op0 = Pc.op0;
-            for (int q = 0; q < nop; ++q) {
-                const OpDesc &o = ops[op0 + (ADJ ? nop - 1 - q : q)];
-                if constexpr (ADJ) {
-                    if (o.gtype != GEN_NONE) {
-                        const double gv = wave_sum(op_gradient<R, NR, RB>(v, w, o));
-                        if (lane == 0) gpart[((size_t)o.gslot * ntiles + tile) * NW + wave] = gv;
-                    }
-                    apply_op<R, NR, RB>(w, o);
-                }
-                apply_op<R, NR, RB>(v, o);
-            }
-        }
-        store_regs<V, R, NR, RB, K>(v, psi + base, tpL, mL);
-        if constexpr (ADJ) store_regs<V, R, NR, RB, K>(w, lam + base, tpL, mL);
-        if constexpr (!PERSIST) break;
-    }
+    store_regs<V, R, NR, RB, K, OFF32>(v, psi + base, tpL, mL);
+    if constexpr (ADJ) store_regs<V, R, NR, RB, K, OFF32>(w, lam + base, tpL, mL);
 }
 
 // ---------------------------------------------------------------------------
@@ -1004,45 +998,24 @@ static int num_cu() {
     return g_num_cu;
 }
 
-// Blocks of a persistent launch: resident blocks per CU times the CU count,
-// capped by the number of tiles.
-template <typename KF>
-static uint32_t persistent_grid(KF kern, int threads, uint64_t ntiles) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess ||
-        per_cu <= 0)
-        per_cu = 1;
-    const uint64_t g = (uint64_t)per_cu * num_cu();
-    return (uint32_t)(ntiles < g ? ntiles : g);
-}
-
-static int g_persist = -1;
-
 template <typename R, int KK, bool ADJ>
 static hipError_t launch_gate_k(void *psi, void *lam, const PassArgs &a, const PhaseDesc *ph,
                                 const OpDesc *ops, double *gpart, hipStream_t s) {
     using V = typename V2T<R>::type;
     constexpr int RB = gate_rb(KK);
     constexpr int NT = 1 << (KK - RB);
-    if (g_persist < 0) {
-        const char *e = std::getenv("SVQ_PERSIST");
-        g_persist = (e && *e) ? std::atoi(e) : 0;
-    }
     if constexpr (sizeof(R) * 2 * (ADJ ? 2 : 1) * (1 << KK) > 160 * 1024) {
         return hipErrorInvalidValue;
     } else {
         const uint32_t ntiles = (uint32_t)a.nblocks;
-        if (g_persist) {
-            auto kern = k_gate_pass<R, KK, RB, ADJ, true>;
-            static uint32_t grid_cache = 0;
-            if (grid_cache == 0) grid_cache = persistent_grid(kern, NT, 1u << 30);
-            const uint32_t grid = ntiles < grid_cache ? ntiles : grid_cache;
-            hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, s, (V *)psi, (V *)lam, a, ph, ops,
-                               gpart, ntiles);
-        } else {
+        // in-tile byte offsets stay below 2^(top tile bit + 1) * sizeof(V)
+        const bool off32 = ((uint64_t)sizeof(V) << (a.tphys[KK - 1] + 1)) <= (1ull << 32);
+        if (off32)
+            hipLaunchKernelGGL((k_gate_pass<R, KK, RB, ADJ, true>), dim3(ntiles), dim3(NT), 0, s,
+                               (V *)psi, (V *)lam, a, ph, ops, gpart, ntiles);
+        else
             hipLaunchKernelGGL((k_gate_pass<R, KK, RB, ADJ, false>), dim3(ntiles), dim3(NT), 0, s,
                                (V *)psi, (V *)lam, a, ph, ops, gpart, ntiles);
-        }
         return hipGetLastError();
     }
 }
