@@ -107,6 +107,23 @@ def measure_main(P, W, torch, args):
     gp_avg_ms = t_gp / max(1, n_gp)
     gp_bytes = 2.0 * S                     # one read + one write of the state per launch
     achieved = gp_bytes / (gp_avg_ms * 1e-3) / 1e9
+    if args.no_eager:
+        st.close()
+        return dict(
+            n=n, g=g, dtype=dtype, m=m, nt=nt, S=S, ms_step=ms_step, qsu_ms=qsu_ms, evc_ms=evc_ms,
+            energy=energy, qsu_evc=None, tuned=tuned,
+            qsu=dict(gates_per_s=m / (qsu_ms * 1e-3), ms=qsu_ms, gate_passes=s1.n_gate_passes,
+                     qr_lazy=s1.n_qr, plan_ms=s1.ms_plan,
+                     algorithmic_gbs=s1.bytes / (qsu_ms * 1e-3) / 1e9,
+                     hbm_frac=s1.bytes / (qsu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     gate_pass_avg_ms=gp_avg_ms, qr_pass_avg_ms=t_qr / max(1, n_qr)),
+            evc=dict(terms_per_s=nt / (evc_ms * 1e-3), ms=evc_ms, evc_passes=s2.n_evc_passes,
+                     groups=s2.n_groups, qr_lazy=s2.n_qr, evc_pass_avg_ms=t_ev / max(1, n_ev),
+                     plan_ms=s2.ms_plan),
+            roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                          kernel="k_gate_pass<float,%d,4,false,true>" % (s1.tile_k or 12),
+                          bytes_per_launch=gp_bytes, launches=n_gp, avg_ms=gp_avg_ms))
     # eager comparison (one run, not part of the timed steps)
     P.sv_set_basis(h, circ.psi0_index)
     torch.cuda.synchronize()
@@ -151,7 +168,7 @@ def measure_main(P, W, torch, args):
         qsu_evc=qsu_evc, tuned=tuned,
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                      kernel="k_gate_pass<float,%d,4,false>" % (s1.tile_k or 12),
+                      kernel="k_gate_pass<float,%d,4,false,true>" % (s1.tile_k or 12),
                       bytes_per_launch=gp_bytes, launches=n_gp, avg_ms=gp_avg_ms),
     )
     return out
@@ -400,6 +417,8 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="run the measured tuner on the workload before timing")
     ap.add_argument("--tune-save", default=None, help="write the tuned table to this file")
+    ap.add_argument("--no-eager", action="store_true",
+                    help="skip the eager-schedule and QSU-based comparisons (profiling runs)")
     ap.add_argument("--qsu-terms", type=int, default=64,
                     help="Pauli strings timed with the QSU-based comparison method (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
