@@ -707,38 +707,68 @@ __global__ __launch_bounds__(1 << evc_tpb(K, sizeof(R) == 8)) void k_evc_pass(
     stage_tile<V, K, TPB, int8_t>(lds, psi + base, a.tphys);
     __syncthreads();
     double acc = 0.0;
+    const char *lb = (const char *)lds;
     for (int gi = 0; gi < a.ngroups; ++gi) {
         const EvcGroup &G = groups[a.group0 + gi];
-        uint32_t tt = 0;
-#pragma unroll
-        for (int b = 0; b < TPB; ++b) tt |= ((threadIdx.x >> b) & 1u) << G.tbits[b];
-        R w[2 * NQ];   // [0, NQ): real / sum array, [NQ, 2NQ): imaginary / difference
-        R *re = w, *im = w + NQ;
+        // every descriptor field first (scalar loads share the LDS counter:
+        // a scalar load between LDS reads would drain them)
         const uint32_t xl = G.xl;
         const int hb = G.hbit;
+        const int need = G.need;
+        const int t0 = G.t0, t1 = G.t0 + G.nt;
+        int tb[TPB], wb[Q > 0 ? Q : 1];
 #pragma unroll
-        for (int jj = 0; jj < NQ; ++jj) {
-            uint32_t j = tt;
+        for (int b = 0; b < TPB; ++b) tb[b] = G.tbits[b];
 #pragma unroll
-            for (int b = 0; b < Q; ++b)
-                if ((jj >> b) & 1) j |= 1u << G.wbits[b];
-            const V x = lds[j];
-            if (xl) {
-                const V p = lds[j ^ xl];
+        for (int b = 0; b < Q; ++b) wb[b] = G.wbits[b];
+        uint32_t tt = 0;
+#pragma unroll
+        for (int b = 0; b < TPB; ++b) tt |= ((threadIdx.x >> b) & 1u) << tb[b];
+        const uint32_t tt8 = tt * (uint32_t)sizeof(V);
+        R w[2 * NQ];   // [0, NQ): real / sum array, [NQ, 2NQ): imaginary / difference
+        R *re = w, *im = w + NQ;
+        V x[NQ], y[NQ];
+        if (xl) {
+            const uint32_t xl8 = xl * (uint32_t)sizeof(V);
+#pragma unroll
+            for (int jj = 0; jj < NQ; ++jj) {
+                uint32_t wo = 0;
+#pragma unroll
+                for (int b = 0; b < Q; ++b)
+                    if ((jj >> b) & 1) wo |= 1u << wb[b];
+                const uint32_t j8 = tt8 | (wo * (uint32_t)sizeof(V));
+                x[jj] = *(const V *)(lb + j8);
+                y[jj] = *(const V *)(lb + (j8 ^ xl8));
+            }
+#pragma unroll
+            for (int jj = 0; jj < NQ; ++jj) {
                 // w = conj(psi_{j^x}) psi_j
-                re[jj] = p.x * x.x + p.y * x.y;
-                im[jj] = p.x * x.y - p.y * x.x;
-            } else {
-                const V y = lds[j | (1u << hb)];
-                const R n0 = x.x * x.x + x.y * x.y, n1 = y.x * y.x + y.y * y.y;
+                re[jj] = y[jj].x * x[jj].x + y[jj].y * x[jj].y;
+                im[jj] = y[jj].x * x[jj].y - y[jj].y * x[jj].x;
+            }
+        } else {
+            const uint32_t hm8 = (1u << hb) * (uint32_t)sizeof(V);
+#pragma unroll
+            for (int jj = 0; jj < NQ; ++jj) {
+                uint32_t wo = 0;
+#pragma unroll
+                for (int b = 0; b < Q; ++b)
+                    if ((jj >> b) & 1) wo |= 1u << wb[b];
+                const uint32_t j8 = tt8 | (wo * (uint32_t)sizeof(V));
+                x[jj] = *(const V *)(lb + j8);
+                y[jj] = *(const V *)(lb + (j8 | hm8));
+            }
+#pragma unroll
+            for (int jj = 0; jj < NQ; ++jj) {
+                const R n0 = x[jj].x * x[jj].x + x[jj].y * x[jj].y;
+                const R n1 = y[jj].x * y[jj].x + y[jj].y * y[jj].y;
                 re[jj] = n0 + n1;
                 im[jj] = n0 - n1;
             }
         }
-        if (G.need & 1) wht<R, NQ>(re);
-        if (G.need & 2) wht<R, NQ>(im);
-        const int t1 = G.t0 + G.nt;
-        for (int ti = G.t0; ti < t1; ++ti) {
+        if (need & 1) wht<R, NQ>(re);
+        if (need & 2) wht<R, NQ>(im);
+        for (int ti = t0; ti < t1; ++ti) {
             const EvcTerm &T = terms[ti];
             const uint32_t wi = (uint32_t)__builtin_amdgcn_readfirstlane(
                 (int)((T.zw & (NQ - 1)) | (T.use_im ? NQ : 0)));
