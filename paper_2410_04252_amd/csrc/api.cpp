@@ -504,7 +504,7 @@ svq_status run_expectation(svq_state st, CachedPaulis *cp, double *energy_dev, d
     PauliPlan &P = cp->plan;
     const int nchunk = 1 << st->g;
     HIPCHK(st, st->d_partials.ensure(sizeof(double) * std::max(1, P.total_blocks)), "alloc partials");
-    HIPCHK(st, st->d_chunks.ensure(sizeof(double) * nchunk), "alloc chunks");
+    HIPCHK(st, st->d_chunks.ensure(sizeof(double) * (nchunk + reduce_scratch(nchunk))), "alloc chunks");
     const int dgrid = direct_grid(st->N());
     HIPCHK(st, st->d_extra.ensure(sizeof(double) * dgrid), "alloc extra");
     double bytes = 0.0;
@@ -533,8 +533,8 @@ svq_status run_expectation(svq_state st, CachedPaulis *cp, double *energy_dev, d
     }
     double *chunks = chunk_dev ? chunk_dev : (double *)st->d_chunks.p;
     HIPCHK(st, launch_reduce_chunks((const double *)st->d_partials.p, (const int *)cp->d_off.p,
-                                    (const int *)cp->d_nblk.p, (int)P.passes.size(), nchunk, chunks,
-                                    st->stream),
+                                    (const int *)cp->d_nblk.p, (int)P.passes.size(), nchunk,
+                                    (double *)st->d_chunks.p + nchunk, chunks, st->stream),
            "reduce");
     HIPCHK(st, launch_finish_energy(chunks, nchunk, (const double *)st->d_extra.p, nextra, energy_dev,
                                     st->stream),

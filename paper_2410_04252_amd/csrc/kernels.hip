@@ -925,22 +925,38 @@ __global__ __launch_bounds__(256) void k_hpsi_direct(const typename V2T<R>::type
 // reductions and small helpers
 // ---------------------------------------------------------------------------
 
-// chunk_out[c] = sum over passes p and within-chunk blocks j of
-// partials[p * per_pass + c * per_chunk + j], in that order.
-__global__ __launch_bounds__(256) void k_reduce_chunks(const double *__restrict__ partials,
-                                                        const int *__restrict__ pass_off,
-                                                        const int *__restrict__ pass_nblk, int npass,
-                                                        int nchunk, double *__restrict__ chunk_out) {
+// Two-level deterministic reduction of the per-block partials into chunk
+// sums.  Level 1: block (c, s) sums, for every pass p in order, the s-th of
+// kReduceSplit equal slices of chunk c's blocks in that pass
+// (partials[pass_off[p] + c * per_chunk + j]); level 2: chunk_out[c] = sum over
+// s of the level-1 values, in order of s.
+constexpr int kReduceSplit = 64;
+
+__global__ __launch_bounds__(256) void k_reduce_chunks_a(const double *__restrict__ partials,
+                                                          const int *__restrict__ pass_off,
+                                                          const int *__restrict__ pass_nblk, int npass,
+                                                          int nchunk, double *__restrict__ tmp) {
     __shared__ double red[4];
-    const int c = blockIdx.x;
+    const int c = blockIdx.x / kReduceSplit, sl = blockIdx.x % kReduceSplit;
     double acc = 0.0;
     for (int p = 0; p < npass; ++p) {
         const int per_chunk = pass_nblk[p] / nchunk;
+        const int j0 = (int)(((long long)per_chunk * sl) / kReduceSplit);
+        const int j1 = (int)(((long long)per_chunk * (sl + 1)) / kReduceSplit);
         const double *src = partials + pass_off[p] + (size_t)c * per_chunk;
-        for (int j = threadIdx.x; j < per_chunk; j += blockDim.x) acc += src[j];
+        for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) acc += src[j];
     }
     const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) chunk_out[c] = s;
+    if (threadIdx.x == 0) tmp[blockIdx.x] = s;
+}
+
+__global__ void k_reduce_chunks_b(const double *__restrict__ tmp, int nchunk,
+                                  double *__restrict__ chunk_out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nchunk) return;
+    double s = 0.0;
+    for (int i = 0; i < kReduceSplit; ++i) s += tmp[c * kReduceSplit + i];
+    chunk_out[c] = s;
 }
 
 // out[0] = extra[0..nextra) + sum_c chunk[c], sequentially.
@@ -1188,10 +1204,14 @@ hipError_t launch_hpsi_direct(bool dbl, const void *psi, void *lam, uint64_t N, 
     return hipGetLastError();
 }
 
+int reduce_scratch(int nchunk) { return nchunk * kReduceSplit; }
+
 hipError_t launch_reduce_chunks(const double *partials, const int *pass_off, const int *pass_nblk,
-                                int npass, int nchunk, double *chunk_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_chunks, dim3(nchunk), dim3(256), 0, s, partials, pass_off, pass_nblk,
-                       npass, nchunk, chunk_out);
+                                int npass, int nchunk, double *tmp, double *chunk_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_chunks_a, dim3(nchunk * kReduceSplit), dim3(256), 0, s, partials,
+                       pass_off, pass_nblk, npass, nchunk, tmp);
+    hipLaunchKernelGGL(k_reduce_chunks_b, dim3((nchunk + 63) / 64), dim3(64), 0, s, tmp, nchunk,
+                       chunk_out);
     return hipGetLastError();
 }
 

@@ -42,8 +42,11 @@ hipError_t launch_evc_direct(bool dbl, const void *psi, uint64_t N, const WideTe
                              double *part, hipStream_t s);
 hipError_t launch_hpsi_direct(bool dbl, const void *psi, void *lam, uint64_t N, const WideTerm *wt,
                               int nw, int accumulate, hipStream_t s);
+// Deterministic chunk sums of the per-block EVC partials; tmp holds
+// reduce_scratch(nchunk) doubles.
+int reduce_scratch(int nchunk);
 hipError_t launch_reduce_chunks(const double *partials, const int *pass_off, const int *pass_nblk,
-                                int npass, int nchunk, double *chunk_out, hipStream_t s);
+                                int npass, int nchunk, double *tmp, double *chunk_out, hipStream_t s);
 hipError_t launch_finish_energy(const double *chunk, int nchunk, const double *extra, int nextra,
                                 double *out, hipStream_t s);
 hipError_t launch_sum(const double *in, int n, double *out, hipStream_t s);

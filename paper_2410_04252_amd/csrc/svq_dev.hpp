@@ -111,6 +111,9 @@ struct EvcTerm {
     int32_t pad;
 };
 
+// The EVC pass reads a term as two 16-byte words per lane.
+static_assert(sizeof(EvcTerm) == 32, "EvcTerm layout");
+
 struct EvcPassArgs {
     int32_t ngroups;
     int32_t group0;
