@@ -552,49 +552,53 @@ __device__ __forceinline__ uint64_t apply_pairs(uint64_t x, const int8_t *pairs,
 
 // No exchanged bit below 6: rows of 64 consecutive elements map to rows, so
 // a wave swaps row r with row pi(r) (once, from the smaller side) with fully
-// coalesced loads and stores.  Each thread handles U rows per iteration so
-// that 2U loads are in flight before the first store.
+// coalesced loads and stores.  Each wave owns U consecutive rows, so that 2U
+// loads are in flight before the first store; one launch covers every row.
 template <typename V, int U>
 __global__ __launch_bounds__(256) void k_qr_rows(V *__restrict__ psi, const QrArgs a) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t nrows = a.nrows;
-    const uint64_t wid = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const uint64_t stride = (uint64_t)gridDim.x * 4 * U;
-    for (uint64_t r0 = wid * U; r0 < nrows; r0 += stride) {
-        V x[U], y[U];
-        uint64_t ra[U], rb[U];
-        bool act[U];
+    const uint64_t r0 = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * U;
+    V x[U], y[U];
+    uint64_t ra[U], rb[U];
+    bool act[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t r = r0 + u;
-            const uint64_t pr = apply_pairs<32>(r << 6, a.outer, a.nouter) >> 6;
-            act[u] = r < nrows && r < pr;
-            ra[u] = (r << 6) | lane;
-            rb[u] = (pr << 6) | lane;
-            if (act[u]) {
-                x[u] = psi[ra[u]];
-                y[u] = psi[rb[u]];
-            }
+    for (int u = 0; u < U; ++u) {
+        const uint64_t r = r0 + u;
+        const uint64_t pr = apply_pairs<32>(r << 6, a.outer, a.nouter) >> 6;
+        act[u] = r < nrows && r < pr;
+        ra[u] = (r << 6) | lane;
+        rb[u] = (pr << 6) | lane;
+        if (act[u]) {
+            x[u] = psi[ra[u]];
+            y[u] = psi[rb[u]];
         }
+    }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (act[u]) {
-                psi[ra[u]] = y[u];
-                psi[rb[u]] = x[u];
-            }
+    for (int u = 0; u < U; ++u) {
+        if (act[u]) {
+            psi[ra[u]] = y[u];
+            psi[rb[u]] = x[u];
         }
     }
 }
 
 // General case: a tile T of TB bits holds the low bits, their partners and
 // further unpaired bits; pi maps tile b to tile pi(b) and permutes inside the
-// tile.  A block swaps the pair (b, pi(b)) once, through LDS so that loads and
-// stores both walk the low bits contiguously.
+// tile.  One block per tile; the block of the smaller tile of a pair (b, pi(b))
+// swaps the two through LDS so that loads and stores both walk the low bits
+// contiguously, the other block exits at once.
 template <typename V, int TB>
 __global__ __launch_bounds__(256) void k_qr_tiles(V *__restrict__ psi, const QrArgs a) {
     constexpr int TS = 1 << TB;
     constexpr int E = TS / 256;
     __shared__ V l0[TS], l1[TS];
+    const uint64_t tile = blockIdx.x;
+    if (tile >= a.ntiles) return;
+    const uint64_t b = spread(tile, a.tphys, TB);
+    const uint64_t pb = apply_pairs<32>(b, a.outer, a.nouter);
+    if (pb < b) return;
+    if (pb == b && a.ninner == 0) return;
     uint64_t off[E];
     uint32_t perm[E];
 #pragma unroll
@@ -607,30 +611,23 @@ __global__ __launch_bounds__(256) void k_qr_tiles(V *__restrict__ psi, const QrA
         off[e] = o;
         perm[e] = (uint32_t)apply_pairs<16>(t, a.inner, a.ninner);
     }
-    for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const uint64_t b = spread(tile, a.tphys, TB);
-        const uint64_t pb = apply_pairs<32>(b, a.outer, a.nouter);
-        if (pb < b) continue;
-        if (pb == b && a.ninner == 0) continue;
-        V x[E], y[E];
+    V x[E], y[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            x[e] = psi[b + off[e]];
-            if (pb != b) y[e] = psi[pb + off[e]];
-        }
+    for (int e = 0; e < E; ++e) {
+        x[e] = psi[b + off[e]];
+        if (pb != b) y[e] = psi[pb + off[e]];
+    }
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            l0[perm[e]] = x[e];
-            if (pb != b) l1[perm[e]] = y[e];
-        }
-        __syncthreads();
+    for (int e = 0; e < E; ++e) {
+        l0[perm[e]] = x[e];
+        if (pb != b) l1[perm[e]] = y[e];
+    }
+    __syncthreads();
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const uint32_t t = threadIdx.x + 256u * e;
-            psi[pb + off[e]] = l0[t];
-            if (pb != b) psi[b + off[e]] = l1[t];
-        }
-        __syncthreads();
+    for (int e = 0; e < E; ++e) {
+        const uint32_t t = threadIdx.x + 256u * e;
+        psi[pb + off[e]] = l0[t];
+        if (pb != b) psi[b + off[e]] = l1[t];
     }
 }
 
@@ -1095,13 +1092,16 @@ hipError_t launch_gate_pass(bool dbl, int k, bool adj, void *psi, void *lam, con
 }
 
 hipError_t launch_qr(bool dbl, void *psi, const QrArgs &a, hipStream_t s) {
-    const int grid = 4 * num_cu();
     if (a.rows_path) {
-        if (dbl) hipLaunchKernelGGL((k_qr_rows<double2, 4>), dim3(grid), dim3(256), 0, s, (double2 *)psi, a);
-        else hipLaunchKernelGGL((k_qr_rows<float2, 4>), dim3(grid), dim3(256), 0, s, (float2 *)psi, a);
+        constexpr int U = 4;
+        const uint64_t nb = (a.nrows + 4 * U - 1) / (4 * U);
+        if (nb > 0x7fffffffULL) return hipErrorInvalidValue;
+        if (dbl) hipLaunchKernelGGL((k_qr_rows<double2, U>), dim3((uint32_t)nb), dim3(256), 0, s, (double2 *)psi, a);
+        else hipLaunchKernelGGL((k_qr_rows<float2, U>), dim3((uint32_t)nb), dim3(256), 0, s, (float2 *)psi, a);
         return hipGetLastError();
     }
-    const uint32_t g2 = (uint32_t)(a.ntiles < (uint64_t)grid ? a.ntiles : (uint64_t)grid);
+    if (a.ntiles > 0x7fffffffULL) return hipErrorInvalidValue;
+    const uint32_t g2 = (uint32_t)a.ntiles;
 #define SVQ_QR_TB(TBV)                                                                                    \
     case TBV:                                                                                             \
         if (dbl) hipLaunchKernelGGL((k_qr_tiles<double2, TBV>), dim3(g2), dim3(256), 0, s, (double2 *)psi, a); \
