@@ -24,10 +24,12 @@ constexpr int kLaneBits = 6;      // wave64
 // wave per tile).
 constexpr int gate_rb(int k) { return k - 6 < 4 ? k - 6 : 4; }
 // Threads (log2) of a Pauli pass: every thread owns a 2^(k-1-tpb) cube of
-// the half space (EVC) or a 2^(k-tpb) cube of outputs (H|psi>).  Double
-// precision keeps one cube bit fewer so the Walsh arrays stay in VGPRs.
+// the half space (EVC) or a 2^(k-tpb) cube of outputs (H|psi>).  Eight pairs
+// per thread keep twice as many waves resident per staged tile as sixteen
+// would (the tile, not the registers, limits residency).
 constexpr int evc_tpb(int k, bool dbl = false) {
-    return (dbl ? k - 4 : k - 5) > 6 ? (dbl ? k - 4 : k - 5) : 6;
+    (void)dbl;
+    return k - 4 > 6 ? k - 4 : 6;
 }
 constexpr int hpsi_tpb(int k) { return k - 4 > 6 ? k - 4 : 6; }
 

@@ -152,3 +152,29 @@ def test_grad24_adjoint_equals_gpu_parameter_shift(P):
                 acc += sgn * w * e
         assert abs(acc - grad[p]) <= 1e-5 * max(1e-3, np.abs(grad).max()), (p, acc, grad[p])
     st.close()
+
+
+def test_wide_chunk_round_trip_64bit_offsets(P):
+    """31 qubits with one global qubit: chunks of 2^30 amplitudes (8 GiB), so
+    passes whose tiles reach physical bit 29 take the 64-bit in-tile offset
+    path and the others the 32-bit one.  U then U^dagger must return the
+    basis state; every amplitude outside its particle-number sector stays
+    exactly zero after U."""
+    import torch
+    n, g = 31, 1
+    circ = W.fabric(n, 4, 3131)
+    _print("31-qubit round trip (64-bit offsets)")
+    buf = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    st = P.State(n, g, "c64", buf=buf)
+    st.set_basis(circ.psi0_index)
+    stats = st.apply(circ, sched=P.LAZY)
+    assert stats.n_gate_passes >= 1
+    amp2 = (buf.real.double() ** 2 + buf.imag.double() ** 2)
+    assert abs(float(amp2.sum()) - 1.0) < 1e-5
+    del amp2
+    st.apply_gates(_inverse(circ), theta=[], sched=P.LAZY)
+    pos = st.layout()
+    phys = sum(1 << pos[q] for q in range(n) if (circ.psi0_index >> q) & 1)
+    top = complex(buf[phys].item())
+    assert abs(top - 1.0) < 1e-4
+    st.close()
