@@ -202,6 +202,46 @@ def measure_qsu_evc(P, W, torch, st, ham, args):
                 pauli_gate_gbs=3.0 * S / (pg_avg * 1e-3) / 1e9 if pg_avg > 0 else None)
 
 
+def measure_c128(P, W, torch, args):
+    """The FP64 path on the same 30-qubit workload (complex128, 16 GiB): lazy
+    QSU and EVC, two timed repetitions after one warm run."""
+    cfg = W.config(args.workload)
+    circ, ham, g = cfg["circuit"], cfg["ham"], cfg["g"]
+    n = circ.n
+    st = P.State(n, g, "c128")
+    h = st.h
+    gc, tc = P.gates_array(circ.gates), P.paulis_array(ham)
+    m, nt = len(circ.gates), len(ham.coef)
+
+    def once():
+        P.sv_set_basis(h, circ.psi0_index)
+        s1 = P.sv_apply_circuit(h, gc, m, circ.theta, len(circ.theta), P.LAZY, 0)
+        e, s2 = P.sv_expectation(h, tc, nt, P.LAZY)
+        return s1, s2, e
+
+    once()
+    torch.cuda.synchronize()
+    P.sv_profile(h, 1)
+    reps = 2
+    for _ in range(reps):
+        s1, s2, e = once()
+    n_gp, t_gp = P.sv_profile_read(h, P.PROF_GATE)
+    n_ev, t_ev = P.sv_profile_read(h, P.PROF_EVC)
+    n_qr, t_qr = P.sv_profile_read(h, P.PROF_QR)
+    P.sv_profile(h, 0)
+    st.close()
+    S = (1 << n) * 16
+    gp_avg = t_gp / max(1, n_gp)
+    qsu_ms = (t_gp + t_qr * s1.n_qr / max(1, s1.n_qr + s2.n_qr)) / reps
+    log(f"[bench] c128: gate pass {gp_avg:.2f} ms ({2 * S / (gp_avg * 1e-3) / 1e9:.0f} GB/s), "
+        f"{s1.n_gate_passes} passes; EVC passes {t_ev / reps:.1f} ms; E={e:.12f}")
+    return dict(workload=args.workload, dtype="c128", gate_passes=s1.n_gate_passes, tile_k=s1.tile_k,
+                gate_pass_avg_ms=gp_avg, gate_pass_gbs=2 * S / (gp_avg * 1e-3) / 1e9,
+                gate_pass_hbm_frac=2 * S / (gp_avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                qsu_gates_per_s_kernels=m / (qsu_ms * 1e-3), evc_pass_ms=t_ev / reps,
+                evc_terms_per_s_kernels=nt / (t_ev / reps * 1e-3), energy=e)
+
+
 def measure_grad(P, W, torch, args):
     cfg = W.config("grad24")
     circ, ham = cfg["circuit"], cfg["ham"]
@@ -413,6 +453,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-c128", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--tune", action="store_true",
                     help="run the measured tuner on the workload before timing")
@@ -459,6 +500,7 @@ def main():
         except Exception:
             traffic = None
     res["roofline"]["traffic"] = traffic
+    c128 = None if (args.no_c128 or res["dtype"] != "c64") else measure_c128(P, W, torch, args)
     grad = None if args.no_grad else measure_grad(P, W, torch, args)
     batch = None if args.no_batch else measure_batch(P, W, torch, args)
     if args.tune_save:
@@ -485,6 +527,7 @@ def main():
         "evc": res["evc"],
         "qsu_evc": res["qsu_evc"],
         "tuned": res["tuned"],
+        "c128": c128,
         "grad": grad,
         "batch": batch,
         "energy": res["energy"],

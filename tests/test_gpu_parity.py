@@ -161,3 +161,51 @@ def test_qr_many_pairs_small_n(P):
             assert np.array_equal(buf.cpu().numpy(), oracle.qr_permute(before, pos, new))
             pos = new
         st.close()
+
+
+ANGLES = [-3 * math.pi, -math.pi, -math.pi / 2 - 1e-3, -1e-7, 0.0, 1e-7, math.pi / 2 + 1e-3,
+          math.pi, 2 * math.pi, 2.5 * math.pi, 7.0]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_unit_modulus_ops_at_boundary_angles(P, dtype):
+    """Rotations and phases near the points where the in-place kernels switch
+    between R(a) and -R(a - pi) (|a| = pi/2), at zero, at multiples of pi and
+    beyond one period, for every unit-modulus kind, on a dense random state."""
+    n, g = 13, 2
+    gates, theta = [], []
+    kinds1 = ["RY", "RZ"]
+    kinds2 = ["GIVENS", "CPHASE"]
+    for i, a in enumerate(ANGLES):
+        q = i % n
+        for kd in kinds1:
+            gates.append((kd, (q,), len(theta)))
+            theta.append(a)
+        for kd in kinds2:
+            gates.append((kd, (q, (q + 5) % n), len(theta)))
+            theta.append(a)
+        gates.append(("CZ", ((q + 1) % n, (q + 7) % n), -1))
+        for kd in ("Z", "S", "T"):
+            gates.append((kd, ((q + 3) % n,), -1))
+    circ = W.Circuit(n, gates, np.array(theta), 0)
+    v = W.random_state(n, 77)
+    ref = oracle.apply_circuit(v, circ.gates, circ.theta)
+    _print(f"boundary angles {dtype}")
+    for sched in (P.LAZY, P.EAGER):
+        st = P.State(n, g, dtype)
+        st.set_amplitudes(v)
+        st.apply(circ, sched=sched)
+        assert np.max(np.abs(st.get_amplitudes() - ref)) < AMP[dtype]
+        st.close()
+    # the adjoint sweep applies the inverses of the same ops
+    ham = W.jw_terms(n, 60, 78)
+    circ0 = W.Circuit(n, gates, np.array(theta), 5)
+    e_ref, g_ref = oracle.adjoint_grad(circ0, ham)
+    st = P.State(n, g, dtype)
+    st.set_basis(5)
+    e, grad, _ = st.grad(circ0, ham)
+    st.close()
+    ok, erel = energy_ok(e, e_ref, None, ham, dtype)
+    assert ok, erel
+    tol = 1e-5 if dtype == "c64" else 1e-11
+    assert np.linalg.norm(grad - g_ref) <= tol * max(1e-3, np.linalg.norm(g_ref))
