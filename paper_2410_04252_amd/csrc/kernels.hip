@@ -1281,18 +1281,17 @@ __device__ void gate_item(const BatchArgs &a, const BatchInst &N, const BatchPas
     const PhaseDesc &P0 = a.phases[bp.phase0 + (ADJ ? np - 1 : 0)];
     const PhaseDesc &PL = a.phases[bp.phase0 + (ADJ ? 0 : np - 1)];
     const uint64_t base = spread(tile, bp.tphys, K);
-    uint32_t tp0, ts0, tpL, tsL;
-    thread_maps<0, K>(P0, bp.tphys, lane, 0u, tp0, ts0);
-    thread_maps<0, K>(PL, bp.tphys, lane, 0u, tpL, tsL);
-    (void)tsL;
-    RegMap<RB, K> m0, mL;
-    m0.init(P0, bp.tphys);
-    mL.init(PL, bp.tphys);
+    // instances have at most 26 qubits: in-tile byte offsets fit 32 bits
     Regs<R, NR> v, w;
-    load_regs<V, R, NR, RB, K>(v, psi + base, tp0, m0);
-    if constexpr (ADJ) load_regs<V, R, NR, RB, K>(w, lam + base, tp0, m0);
-    uint32_t sw = ts0;
-    RegMap<RB, K> mc = m0;
+    uint32_t sw;
+    RegMap<RB, K> mc;
+    {
+        uint32_t tp0;
+        thread_maps<0, K>(P0, bp.tphys, lane, 0u, tp0, sw);
+        mc.init(P0, bp.tphys);
+        load_regs<V, R, NR, RB, K, true>(v, psi + base, tp0, mc);
+        if constexpr (ADJ) load_regs<V, R, NR, RB, K, true>(w, lam + base, tp0, mc);
+    }
     for (int s = 0; s < np; ++s) {
         const PhaseDesc &Pc = a.phases[bp.phase0 + (ADJ ? np - 1 - s : s)];
         if (s > 0) {
@@ -1338,8 +1337,13 @@ __device__ void gate_item(const BatchArgs &a, const BatchInst &N, const BatchPas
             apply_op<R, NR, RB>(v, o);
         }
     }
-    store_regs<V, R, NR, RB, K>(v, psi + base, tpL, mL);
-    if constexpr (ADJ) store_regs<V, R, NR, RB, K>(w, lam + base, tpL, mL);
+    uint32_t tpL, tsL;
+    thread_maps<0, K>(PL, bp.tphys, lane, 0u, tpL, tsL);
+    (void)tsL;
+    RegMap<RB, K> mL;
+    mL.init(PL, bp.tphys);
+    store_regs<V, R, NR, RB, K, true>(v, psi + base, tpL, mL);
+    if constexpr (ADJ) store_regs<V, R, NR, RB, K, true>(w, lam + base, tpL, mL);
 }
 
 __device__ void hpsi_item(const BatchArgs &a, const BatchInst &N, const BatchHPass &hp, int accumulate,
