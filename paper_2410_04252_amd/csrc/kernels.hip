@@ -721,7 +721,10 @@ __global__ __launch_bounds__(1 << evc_tpb(K, sizeof(R) == 8)) void k_evc_pass(
         uint32_t tt = 0;
 #pragma unroll
         for (int b = 0; b < TPB; ++b) tt |= ((threadIdx.x >> b) & 1u) << tb[b];
-        const uint32_t tt8 = tt * (uint32_t)sizeof(V);
+        uint32_t tt8 = tt * (uint32_t)sizeof(V);
+        // keep the byte offset opaque: otherwise (tt8 | wo8) is rewritten as
+        // (tt | wo) * 8, one extra shift per LDS address
+        asm volatile("" : "+v"(tt8));
         R w[2 * NQ];   // [0, NQ): real / sum array, [NQ, 2NQ): imaginary / difference
         R *re = w, *im = w + NQ;
         V x[NQ], y[NQ];
@@ -765,7 +768,23 @@ __global__ __launch_bounds__(1 << evc_tpb(K, sizeof(R) == 8)) void k_evc_pass(
         }
         if (need & 1) wht<R, NQ>(re);
         if (need & 2) wht<R, NQ>(im);
-        for (int ti = t0; ti < t1; ++ti) {
+        // terms four at a time: all descriptor loads first, then one wait
+        int ti = t0;
+        for (; ti + 4 <= t1; ti += 4) {
+            EvcTerm T[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) T[u] = terms[ti + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t wi = (uint32_t)__builtin_amdgcn_readfirstlane(
+                    (int)((T[u].zw & (NQ - 1)) | (T[u].use_im ? NQ : 0)));
+                const R val = w[wi];
+                const uint32_t par =
+                    (__builtin_popcount(tt & T[u].zt) + __builtin_popcountll(base & T[u].zg)) & 1u;
+                acc += T[u].coef * (double)(par ? -val : val);
+            }
+        }
+        for (; ti < t1; ++ti) {
             const EvcTerm &T = terms[ti];
             const uint32_t wi = (uint32_t)__builtin_amdgcn_readfirstlane(
                 (int)((T.zw & (NQ - 1)) | (T.use_im ? NQ : 0)));
