@@ -740,11 +740,13 @@ __global__ __launch_bounds__(1 << evc_tpb(K, sizeof(R) == 8)) void k_evc_pass(
                 x[jj] = *(const V *)(lb + j8);
                 y[jj] = *(const V *)(lb + (j8 ^ xl8));
             }
+            // w = conj(psi_{j^x}) psi_j; the imaginary part only when a term
+            // of the group reads it (an odd number of Y)
 #pragma unroll
-            for (int jj = 0; jj < NQ; ++jj) {
-                // w = conj(psi_{j^x}) psi_j
-                re[jj] = y[jj].x * x[jj].x + y[jj].y * x[jj].y;
-                im[jj] = y[jj].x * x[jj].y - y[jj].y * x[jj].x;
+            for (int jj = 0; jj < NQ; ++jj) re[jj] = y[jj].x * x[jj].x + y[jj].y * x[jj].y;
+            if (need & 2) {
+#pragma unroll
+                for (int jj = 0; jj < NQ; ++jj) im[jj] = y[jj].x * x[jj].y - y[jj].y * x[jj].x;
             }
         } else {
             const uint32_t hm8 = (1u << hb) * (uint32_t)sizeof(V);
