@@ -172,6 +172,45 @@ static uint64_t qubit_mapping_fill(uint64_t universe, const std::vector<int> &re
     return QL;
 }
 
+// Level-2 pass set (our own packing; the paper's tiling has one level): the
+// local-set greedy of Alg. 3 is one candidate; the other grows the set from
+// the forced bits by repeatedly adding the frontier gate (every earlier gate
+// on its qubits already in the pass) that needs the fewest new qubits, which
+// keeps light cones compact.  The candidate whose pass holds more gates wins.
+static uint64_t choose_pass_set(uint64_t universe, uint64_t forced, const std::vector<int> &remain,
+                                const std::vector<uint64_t> &targets, int budget) {
+    const uint64_t a = qubit_mapping(universe, forced, remain, targets, budget);
+    const size_t na = tile_construction(a, remain, targets).size();
+    uint64_t S = forced;
+    for (;;) {
+        // gates executable inside S, then the frontier just behind them
+        uint64_t avail = S, blocked = 0;
+        int pick = -1, pick_new = 99;
+        for (int i : remain) {
+            const uint64_t T = targets[i];
+            if ((T & ~avail) == 0) continue;   // inside the pass
+            avail &= ~T;
+            // blocked: qubits of every earlier gate outside the pass; a gate
+            // on none of them is on the frontier and (as T is not inside
+            // S & ~blocked) needs at least one new qubit
+            const bool frontier = (T & blocked) == 0;
+            blocked |= T;
+            if (!frontier) continue;
+            const int nw = popc(T & ~S);
+            if (nw > 0 && popc(S) + nw <= budget && nw < pick_new) {
+                pick = i;
+                pick_new = nw;
+            }
+        }
+        if (pick < 0) break;
+        S |= targets[pick];
+    }
+    for (uint64_t free = universe & ~S; popc(S) < budget && free; free &= free - 1)
+        S |= free & (~free + 1);
+    const size_t nb = tile_construction(S, remain, targets).size();
+    return nb > na ? S : a;
+}
+
 static uint64_t local_set(const std::vector<int> &pos, int nL) {
     uint64_t s = 0;
     for (size_t q = 0; q < pos.size(); ++q)
@@ -657,7 +696,7 @@ std::string plan_circuit(int n, int g, const std::vector<GateN> &gates, svq_sche
         for (int i : T.ops) pt[i] = phys_mask(targets[i], lay);
         std::vector<int> remain = T.ops;
         while (!remain.empty()) {
-            uint64_t S = qubit_mapping(localpos, forced, remain, pt, keff);
+            uint64_t S = choose_pass_set(localpos, forced, remain, pt, keff);
             std::vector<int> G = tile_construction(S, remain, pt);
             if (G.empty()) return "internal: empty gate pass";
             std::vector<char> tk(m, 0);
