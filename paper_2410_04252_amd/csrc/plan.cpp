@@ -555,17 +555,55 @@ static void plan_phases(int k, int rb, const std::vector<L3Gate> &gs, CircuitPla
             else avail &= ~(uint64_t)gs[i].t;
             if (!avail) break;
         }
-        // fill with the highest tile bits outside the coalescing lanes first
-        for (int b = k - 1; b >= 6 && popc(regs) < rb; --b) regs |= 1u << b;
-        for (int b = k - 1; b >= 0 && popc(regs) < rb; --b) regs |= 1u << b;
+        auto fill = [&](uint64_t r) {
+            // fill with the highest tile bits outside the coalescing lanes first
+            for (int b = k - 1; b >= 6 && popc(r) < rb; --b) r |= 1u << b;
+            for (int b = k - 1; b >= 0 && popc(r) < rb; --b) r |= 1u << b;
+            return r;
+        };
         // tile construction with dependency blocking on all targets
-        uint64_t av = all;
-        std::vector<int> G;
-        for (int i : remain) {
-            const L3Gate &g = gs[i];
-            if ((g.t & ~av) == 0 && (g.mix & ~regs) == 0) G.push_back(i);
-            else av &= ~(uint64_t)g.t;
-            if (!av) break;
+        auto phase_gates = [&](uint64_t r) {
+            uint64_t av = all;
+            std::vector<int> out;
+            for (int i : remain) {
+                const L3Gate &g = gs[i];
+                if ((g.t & ~av) == 0 && (g.mix & ~r) == 0) out.push_back(i);
+                else av &= ~(uint64_t)g.t;
+                if (!av) break;
+            }
+            return out;
+        };
+        regs = fill(regs);
+        std::vector<int> G = phase_gates(regs);
+        {
+            // second candidate: grow the register set by the frontier gate
+            // that needs the fewest new register bits
+            uint64_t r2 = 0;
+            for (;;) {
+                uint64_t av = all, blocked = 0;
+                int pick = -1, pick_new = 99;
+                for (int i : remain) {
+                    const L3Gate &g = gs[i];
+                    if ((g.t & ~av) == 0 && (g.mix & ~r2) == 0) continue;   // runs now
+                    av &= ~(uint64_t)g.t;
+                    const bool frontier = (g.t & blocked) == 0;
+                    blocked |= g.t;
+                    if (!frontier) continue;
+                    const int nw = popc(g.mix & ~r2);
+                    if (nw > 0 && popc(r2 | g.mix) <= rb && nw < pick_new) {
+                        pick = i;
+                        pick_new = nw;
+                    }
+                }
+                if (pick < 0) break;
+                r2 |= gs[pick].mix;
+            }
+            r2 = fill(r2);
+            std::vector<int> G2 = phase_gates(r2);
+            if (G2.size() > G.size()) {
+                regs = r2;
+                G.swap(G2);
+            }
         }
         std::vector<char> tk(gs.size(), 0);
         for (int i : G) tk[i] = 1;
