@@ -174,6 +174,35 @@ def measure_main(P, W, torch, args):
     return out
 
 
+def measure_copy_gbs(torch):
+    """Achievable device bandwidth: a plain 8 GiB -> 8 GiB torch copy (bytes
+    read + written over the kernel time, best of three)."""
+    a = torch.empty(1 << 30, dtype=torch.complex64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    best = 1e30
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (1 << 30) * 8 / (best * 1e-3) / 1e9
+
+
+def qr_trend(P, W):
+    """The paper's trend configuration on the host planner: GateFabric with
+    4n layers at 30 qubits, one operator per 4-qubit block, g = 5."""
+    ops = W.block_ops(30, 120)
+    return dict(n=30, layers=120, block_ops=len(ops),
+                flat=P.sv_plan_ops(30, 25, ops, P.PLAN_FLAT)["n_qr"],
+                adhoc=P.sv_plan_ops(30, 25, ops, P.PLAN_ADHOC)["n_qr"])
+
+
 def measure_qsu_evc(P, W, torch, st, ham, args):
     """The QSU-based comparison method on the first qsu_terms strings (index
     order): each string applied as a gate into psi' (one elementwise pass per
@@ -398,7 +427,22 @@ def measure_cpu(W, main, budget_s):
         t_e += time.perf_counter() - t0
         terms_done += 1
     del psi
+    cpu_model, ram_gib = None, None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    ram_gib = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
     return dict(value=done / t_q, unit="gates/s", cores=oracle.threads(), kind="oracle",
+                cpu_model=cpu_model, ram_gib=ram_gib,
                 sample=f"first {done} gates of the {n}-qubit circuit on a 2^{n} complex128 state "
                        f"({t_q:.1f} s); EVC: {terms_done} Pauli strings ({t_e:.1f} s)",
                 evc_terms_per_s=terms_done / t_e)
@@ -500,6 +544,13 @@ def main():
         except Exception:
             traffic = None
     res["roofline"]["traffic"] = traffic
+    if not args.no_eager:
+        copy_gbs = measure_copy_gbs(torch)
+        res["roofline"]["copy_gbs"] = round(copy_gbs, 1)
+        res["roofline"]["frac_of_torch_copy"] = round(res["roofline"]["achieved"] / copy_gbs, 4)
+        log(f"[bench] plain device copy {copy_gbs:.0f} GB/s; gate pass at "
+            f"{res['roofline']['frac_of_torch_copy'] * 100:.1f}% of it")
+        res["qsu"]["qr_trend_30q_120_layers"] = qr_trend(P, W)
     c128 = None if (args.no_c128 or res["dtype"] != "c64") else measure_c128(P, W, torch, args)
     grad = None if args.no_grad else measure_grad(P, W, torch, args)
     batch = None if args.no_batch else measure_batch(P, W, torch, args)

@@ -178,3 +178,56 @@ def test_wide_chunk_round_trip_64bit_offsets(P):
     top = complex(buf[phys].item())
     assert abs(top - 1.0) < 1e-4
     st.close()
+
+
+def _product_expectation(ham, t, f):
+    want = 0.0
+    for k in range(len(ham.coef)):
+        x, z = int(ham.x[k]), int(ham.z[k])
+        v = 1.0
+        for q in range(ham.n):
+            xb, zb = (x >> q) & 1, (z >> q) & 1
+            if xb and zb:
+                v *= math.sin(t[q]) * math.sin(f[q])
+            elif xb:
+                v *= math.sin(t[q]) * math.cos(f[q])
+            elif zb:
+                v *= math.cos(t[q])
+            if v == 0.0:
+                break
+        want += ham.coef[k] * v
+    return want
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_fabric32_evc_product_state_and_round_trip(P, dtype):
+    """The 32-qubit configuration (g = 6, 10^4 JW-like strings), c64 (32 GiB)
+    and c128 (64 GiB): EVC of a product state against its closed form, then
+    the 360-gate fabric circuit and its inverse return the basis state."""
+    cfg = W.config("fabric32")
+    circ, ham, g = cfg["circuit"], cfg["ham"], cfg["g"]
+    n = ham.n
+    pc, t, f = W.product_state_circuit(n, 3232)
+    want = _product_expectation(ham, t, f)
+    _print(f"fabric32 {dtype} product-state EVC")
+    import torch
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    buf = torch.empty(1 << n, dtype=tdt, device="cuda")
+    st = P.State(n, g, dtype, buf=buf)
+    st.set_basis(0)
+    st.apply(pc)
+    e, stats = st.expectation(ham)
+    assert stats.n_qr <= 8
+    assert abs(e - want) <= ENERGY_REL[dtype] * energy_scale(want, ham), (e, want)
+    _print(f"fabric32 {dtype} round trip")
+    st.set_basis(circ.psi0_index)
+    s1 = st.apply(circ)
+    assert s1.n_qr <= 4
+    st.apply_gates(_inverse(circ), theta=[], sched=P.LAZY)
+    pos = st.layout()
+    phys = sum(1 << pos[q] for q in range(n) if (circ.psi0_index >> q) & 1)
+    top = complex(buf[phys].item())
+    assert abs(top - 1.0) < (1e-4 if dtype == "c64" else 1e-10), top
+    st.close()
+    del buf
+    torch.cuda.empty_cache()
