@@ -188,7 +188,7 @@ int default_c(const svq_state_s *st) {
 // Pauli passes are read-only: a wider tile covers more flip masks per read.
 int default_evc_k(const svq_state_s *st) {
     TuneVal tv;
-    int k = st->dbl() ? 13 : 14;
+    int k = 12;   // the measured best at 28-32 qubits for both precisions
     if (tuned(1, st->n, st->g, (int)st->dtype, tv)) k = tv.k;
     k = env_int("SVQ_EVC_K", k);
     // one staged tile must fit the 128 KiB the EVC pass reserves in LDS
