@@ -517,7 +517,7 @@ def main():
         ingest_pmc(*args.ingest_pmc, tile_k=args.tile_k)
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: measures one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_calib:

@@ -52,7 +52,7 @@ typedef enum {
     SVQ_ENOMEM = -2,     /* device or host allocation failed */
     SVQ_EHIP = -3,       /* a HIP call failed; the handle is poisoned */
     SVQ_ESHAPE = -4,     /* sizes inconsistent (buffer too small, n out of range) */
-    SVQ_EUNSUP = -5,     /* valid but not supported by this build */
+    SVQ_EUNSUP = -5,     /* valid but not supported by this library */
     SVQ_EPOISONED = -6   /* an earlier HIP failure poisoned the handle */
 } svq_status;
 

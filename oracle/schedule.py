@@ -17,7 +17,7 @@ Operators are given by their target sets T(C_i) (tuples of qubits); a tile is
   then the X/Y support only, eq. without_QR / eq. par_exp).
 * :func:`n_qr` -- eq. n_qr with the indicator reading of eq. f_eq.
 
-Readings where the paper is ambiguous (each also listed in the design doc):
+Readings where the paper is ambiguous:
 * Alg. 1 increments x before removing g(x); read as "remove the operator just
   scheduled, then increment".
 * eq. f_eq calls delta a Kronecker delta but returns 1 when the arguments
