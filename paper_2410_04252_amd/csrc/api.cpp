@@ -212,11 +212,18 @@ QrArgs make_qr_args(int n, bool dbl, const std::vector<Transposition> &tr) {
     if (n >= 7 && low >= 6) {
         a.rows_path = 1;
         a.nrows = 1ULL << (n - 6);
+        int top = -1, partner_of_top = -1;
         for (const auto &t : tr) {
             a.outer[2 * a.nouter] = (int8_t)t.a;
             a.outer[2 * a.nouter + 1] = (int8_t)t.b;
             a.nouter++;
+            if (std::max(t.a, t.b) > top) {
+                top = std::max(t.a, t.b);
+                partner_of_top = std::min(t.a, t.b);
+            }
         }
+        a.hbit = top - 6;
+        a.lbit = partner_of_top - 6;
         return a;
     }
     int partner[64];

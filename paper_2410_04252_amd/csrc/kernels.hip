@@ -557,16 +557,30 @@ __device__ __forceinline__ uint64_t apply_pairs(uint64_t x, const int8_t *pairs,
 template <typename V, int U>
 __global__ __launch_bounds__(256) void k_qr_rows(V *__restrict__ psi, const QrArgs a) {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t nrows = a.nrows;
+    // Let h be the highest exchanged row bit and l its partner.  A row with
+    // bits (h, l) = (1, 0) is the larger side of its pair, so rows are
+    // enumerated as those with h = 0 (the first half), then those with
+    // h = l = 1 (a quarter): three quarters of the rows, no wave idle on the
+    // (1, 0) quarter.
+    const uint64_t nhalf = a.nrows >> 1, nenum = nhalf + (a.nrows >> 2);
+    const int h = a.hbit, l = a.lbit;
     const uint64_t r0 = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * U;
     V x[U], y[U];
     uint64_t ra[U], rb[U];
     bool act[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const uint64_t r = r0 + u;
+        const uint64_t i = r0 + u;
+        uint64_t r;
+        if (i < nhalf) {
+            r = ((i >> h) << (h + 1)) | (i & ((1ULL << h) - 1));
+        } else {
+            const uint64_t j = i - nhalf;
+            const uint64_t t = ((j >> l) << (l + 1)) | (1ULL << l) | (j & ((1ULL << l) - 1));
+            r = ((t >> h) << (h + 1)) | (1ULL << h) | (t & ((1ULL << h) - 1));
+        }
         const uint64_t pr = apply_pairs<32>(r << 6, a.outer, a.nouter) >> 6;
-        act[u] = r < nrows && r < pr;
+        act[u] = i < nenum && r < pr;
         ra[u] = (r << 6) | lane;
         rb[u] = (pr << 6) | lane;
         if (act[u]) {
@@ -1115,7 +1129,7 @@ hipError_t launch_gate_pass(bool dbl, int k, bool adj, void *psi, void *lam, con
 hipError_t launch_qr(bool dbl, void *psi, const QrArgs &a, hipStream_t s) {
     if (a.rows_path) {
         constexpr int U = 4;
-        const uint64_t nb = (a.nrows + 4 * U - 1) / (4 * U);
+        const uint64_t nb = ((a.nrows >> 1) + (a.nrows >> 2) + 4 * U - 1) / (4 * U);
         if (nb > 0x7fffffffULL) return hipErrorInvalidValue;
         if (dbl) hipLaunchKernelGGL((k_qr_rows<double2, U>), dim3((uint32_t)nb), dim3(256), 0, s, (double2 *)psi, a);
         else hipLaunchKernelGGL((k_qr_rows<float2, U>), dim3((uint32_t)nb), dim3(256), 0, s, (float2 *)psi, a);

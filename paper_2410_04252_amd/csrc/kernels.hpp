@@ -14,6 +14,7 @@ struct QrArgs {
     int32_t nouter;         // transpositions outside the tile (rows path: all of them)
     int32_t ninner;         // transpositions inside the tile (tile-local bits)
     int32_t rows_path;      // 1: no exchanged bit below 6, swap rows of 64 elements
+    int32_t hbit, lbit;     // rows path: row bits of the highest exchanged bit and its partner
     uint64_t ntiles;        // 2^(n - tbits)
     uint64_t nrows;         // 2^(n - 6)
     int8_t tphys[16];       // physical bit of tile-local bit j (ascending)
