@@ -271,6 +271,20 @@ QrArgs make_qr_args(int n, bool dbl, const std::vector<Transposition> &tr) {
             a.nouter++;
         }
     }
+    // tile path with outer pairs: positions, among the non-tile bits (the
+    // tile index), of the highest outer bit and its partner
+    int top = -1, ptop = -1;
+    for (int i = 0; i < a.nouter; ++i) {
+        const int x = a.outer[2 * i], y = a.outer[2 * i + 1];
+        if (std::max(x, y) > top) {
+            top = std::max(x, y);
+            ptop = std::min(x, y);
+        }
+    }
+    if (top >= 0) {
+        a.hbit = top - __builtin_popcountll(T & ((1ULL << top) - 1));
+        a.lbit = ptop - __builtin_popcountll(T & ((1ULL << ptop) - 1));
+    }
     return a;
 }
 

@@ -607,8 +607,23 @@ __global__ __launch_bounds__(256) void k_qr_tiles(V *__restrict__ psi, const QrA
     constexpr int TS = 1 << TB;
     constexpr int E = TS / 256;
     __shared__ V l0[TS], l1[TS];
-    const uint64_t tile = blockIdx.x;
-    if (tile >= a.ntiles) return;
+    // With outer pairs, tiles are enumerated like the rows of k_qr_rows: the
+    // highest outer bit h = 0 (first half), then h = l = 1 (a quarter).
+    uint64_t tile = blockIdx.x;
+    if (a.nouter) {
+        const uint64_t nhalf = a.ntiles >> 1;
+        if (tile >= nhalf + (a.ntiles >> 2)) return;
+        const int h = a.hbit, l = a.lbit;
+        if (tile < nhalf) {
+            tile = ((tile >> h) << (h + 1)) | (tile & ((1ULL << h) - 1));
+        } else {
+            const uint64_t j = tile - nhalf;
+            const uint64_t t = ((j >> l) << (l + 1)) | (1ULL << l) | (j & ((1ULL << l) - 1));
+            tile = ((t >> h) << (h + 1)) | (1ULL << h) | (t & ((1ULL << h) - 1));
+        }
+    } else if (tile >= a.ntiles) {
+        return;
+    }
     const uint64_t b = spread(tile, a.tphys, TB);
     const uint64_t pb = apply_pairs<32>(b, a.outer, a.nouter);
     if (pb < b) return;
@@ -1136,7 +1151,7 @@ hipError_t launch_qr(bool dbl, void *psi, const QrArgs &a, hipStream_t s) {
         return hipGetLastError();
     }
     if (a.ntiles > 0x7fffffffULL) return hipErrorInvalidValue;
-    const uint32_t g2 = (uint32_t)a.ntiles;
+    const uint32_t g2 = (uint32_t)(a.nouter ? (a.ntiles >> 1) + (a.ntiles >> 2) : a.ntiles);
 #define SVQ_QR_TB(TBV)                                                                                    \
     case TBV:                                                                                             \
         if (dbl) hipLaunchKernelGGL((k_qr_tiles<double2, TBV>), dim3(g2), dim3(256), 0, s, (double2 *)psi, a); \
