@@ -209,3 +209,32 @@ def test_unit_modulus_ops_at_boundary_angles(P, dtype):
     assert ok, erel
     tol = 1e-5 if dtype == "c64" else 1e-11
     assert np.linalg.norm(grad - g_ref) <= tol * max(1e-3, np.linalg.norm(g_ref))
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("swaps", [((7, 12), (8, 13)), ((6, 11),), ((1, 12), (9, 13)),
+                                   ((0, 13), (10, 12), (6, 11))],
+                         ids=["rows-2", "rows-1", "tiles-inner-outer", "tiles-mixed"])
+def test_qr_paths_with_outer_pairs(P, dtype, swaps):
+    """Reorders that take the rows path (every exchanged bit at 6 or above)
+    and the tile path with pairs outside the tile, where only the rows or
+    tiles that can be the smaller side of their pair are launched."""
+    import torch
+    n, g = 14, 3
+    v = W.random_state(n, 90 + len(swaps), np.complex64 if dtype == "c64" else np.complex128)
+    buf = torch.empty(1 << n, dtype=torch.complex64 if dtype == "c64" else torch.complex128,
+                      device="cuda")
+    st = P.State(n, g, dtype, buf=buf)
+    st.set_amplitudes(v)
+    pos = list(range(n))
+    phys = list(range(n))
+    for a, b in swaps:
+        phys[a], phys[b] = phys[b], phys[a]
+    new = [phys[p] for p in pos]
+    _print(f"qr paths {swaps} {dtype}")
+    before = buf.cpu().numpy().copy()
+    st.qr_permute(new)
+    torch.cuda.synchronize()
+    assert np.array_equal(buf.cpu().numpy(), oracle.qr_permute(before, pos, new))
+    np.testing.assert_array_equal(st.get_amplitudes(), v)
+    st.close()
