@@ -172,18 +172,17 @@ static uint64_t qubit_mapping_fill(uint64_t universe, const std::vector<int> &re
     return QL;
 }
 
-// Level-2 pass set (our own packing; the paper's tiling has one level): the
-// local-set greedy of Alg. 3 is one candidate; the other grows the set from
-// the forced bits by repeatedly adding the frontier gate (every earlier gate
-// on its qubits already in the pass) that needs the fewest new qubits, which
-// keeps light cones compact.  The candidate whose pass holds more gates wins.
-static uint64_t choose_pass_set(uint64_t universe, uint64_t forced, const std::vector<int> &remain,
-                                const std::vector<uint64_t> &targets, int budget) {
-    const uint64_t a = qubit_mapping(universe, forced, remain, targets, budget);
-    const size_t na = tile_construction(a, remain, targets).size();
+// Level-2 pass set (our own packing; the paper's tiling has one level).  Two
+// greedy candidates: the local-set greedy of Alg. 3, and a set grown from the
+// forced bits by repeatedly adding the frontier gate (every earlier gate on
+// its qubits already in the pass) that needs the fewest new qubits, which
+// keeps light cones compact.
+static void pass_candidates(uint64_t universe, uint64_t forced, const std::vector<int> &remain,
+                            const std::vector<uint64_t> &targets, int budget, uint64_t &a,
+                            uint64_t &b) {
+    a = qubit_mapping(universe, forced, remain, targets, budget);
     uint64_t S = forced;
     for (;;) {
-        // gates executable inside S, then the frontier just behind them
         uint64_t avail = S, blocked = 0;
         int pick = -1, pick_new = 99;
         for (int i : remain) {
@@ -207,8 +206,53 @@ static uint64_t choose_pass_set(uint64_t universe, uint64_t forced, const std::v
     }
     for (uint64_t free = universe & ~S; popc(S) < budget && free; free &= free - 1)
         S |= free & (~free + 1);
-    const size_t nb = tile_construction(S, remain, targets).size();
-    return nb > na ? S : a;
+    b = S;
+}
+
+static std::vector<int> without(const std::vector<int> &remain, const std::vector<int> &G, int m) {
+    std::vector<char> tk(m, 0);
+    for (int i : G) tk[i] = 1;
+    std::vector<int> rest;
+    rest.reserve(remain.size());
+    for (int i : remain)
+        if (!tk[i]) rest.push_back(i);
+    return rest;
+}
+
+// The candidate whose pass holds more gates (ties: the Alg. 3 one).
+static uint64_t fuller_pass(uint64_t universe, uint64_t forced, const std::vector<int> &remain,
+                            const std::vector<uint64_t> &targets, int budget) {
+    uint64_t a, b;
+    pass_candidates(universe, forced, remain, targets, budget, a, b);
+    return tile_construction(b, remain, targets).size() > tile_construction(a, remain, targets).size()
+               ? b : a;
+}
+
+// Pick between the two candidates by completing each with fuller_pass and
+// counting the passes; fewer passes win, then more gates in this pass.
+static uint64_t choose_pass_set(uint64_t universe, uint64_t forced, const std::vector<int> &remain,
+                                const std::vector<uint64_t> &targets, int budget) {
+    uint64_t a, b;
+    pass_candidates(universe, forced, remain, targets, budget, a, b);
+    const std::vector<int> Ga = tile_construction(a, remain, targets);
+    const std::vector<int> Gb = tile_construction(b, remain, targets);
+    if (a == b || Gb.empty()) return a;
+    if (Ga.empty()) return b;
+    const int m = (int)targets.size();
+    auto rollout = [&](std::vector<int> rest) {
+        int passes = 0;
+        while (!rest.empty()) {
+            const uint64_t S = fuller_pass(universe, forced, rest, targets, budget);
+            const std::vector<int> G = tile_construction(S, rest, targets);
+            if (G.empty()) return 1 << 20;
+            rest = without(rest, G, m);
+            ++passes;
+        }
+        return passes;
+    };
+    const int pa = rollout(without(remain, Ga, m)), pb = rollout(without(remain, Gb, m));
+    if (pa != pb) return pa < pb ? a : b;
+    return Gb.size() > Ga.size() ? b : a;
 }
 
 static uint64_t local_set(const std::vector<int> &pos, int nL) {
