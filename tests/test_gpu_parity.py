@@ -238,3 +238,73 @@ def test_qr_paths_with_outer_pairs(P, dtype, swaps):
     assert np.array_equal(buf.cpu().numpy(), oracle.qr_permute(before, pos, new))
     np.testing.assert_array_equal(st.get_amplitudes(), v)
     st.close()
+
+
+def _haar(rng, d):
+    z = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def _dense_circuit(n, seed):
+    """Dense U1/U2 blocks (Haar-random unitaries, row-major, q[0] the least
+    significant bit of the local index) between RY/GIVENS layers."""
+    rng = np.random.default_rng(seed)
+    gates, theta = [], []
+    for layer in range(3):
+        for q in range(0, n - 1, 2):
+            gates.append(("U2", (q + layer % 2, (q + 3) % n), -1, _haar(rng, 4)))
+        for q in range(n):
+            gates.append(("U1", (q,), -1, _haar(rng, 2)))
+            gates.append(("RY", (q,), len(theta)))
+            theta.append(float(rng.uniform(-math.pi, math.pi)))
+        for q in range(0, n - 2, 3):
+            gates.append(("GIVENS", (q, q + 2), len(theta)))
+            theta.append(float(rng.uniform(-math.pi, math.pi)))
+    return gates, np.array(theta)
+
+
+def _oracle_run(n, gates, theta, psi):
+    for gt in gates:
+        kind, qs, p = gt[0], gt[1], gt[2]
+        if kind in ("U1", "U2"):
+            psi = oracle.apply_gate(psi, kind, qs, umat=gt[3])
+        else:
+            psi = oracle.apply_gate(psi, kind, qs, angle=theta[p] if p >= 0 else 0.0)
+    return psi
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_dense_matrix_gates_forward_and_gradient(P, dtype):
+    """U1/U2 user matrices through the C ABI: forward parity under both
+    schedules, and the adjoint gradient (which applies their conjugate
+    transposes) against the oracle's exact parameter-shift gradient."""
+    n, g = 11, 2
+    gates, theta = _dense_circuit(n, 404)
+    psi0 = oracle.basis_state(n, 3)
+    ref = _oracle_run(n, gates, theta, psi0)
+    _print(f"dense gates {dtype}")
+    for sched in (P.LAZY, P.EAGER):
+        st = P.State(n, g, dtype)
+        st.set_basis(3)
+        st.apply_gates(gates, theta=theta, sched=sched)
+        assert np.max(np.abs(st.get_amplitudes() - ref)) < AMP[dtype]
+        st.close()
+    ham = W.jw_terms(n, 40, 405)
+    kind_of = {gt[2]: gt[0] for gt in gates if gt[2] >= 0}
+    g_ref = np.zeros(len(theta))
+    for p in range(len(theta)):
+        for shift, w in oracle.SHIFT_RULES[kind_of[p]]:
+            for sgn in (+1, -1):
+                th = theta.copy()
+                th[p] += sgn * shift
+                g_ref[p] += sgn * w * oracle.expectation(_oracle_run(n, gates, th, psi0), ham)
+    circ = W.Circuit(n, gates, theta, 3)
+    st = P.State(n, g, dtype)
+    st.set_basis(3)
+    e, grad, _ = st.grad(circ, ham)
+    st.close()
+    ok, rel = energy_ok(e, oracle.expectation(ref, ham), ref, ham, dtype)
+    assert ok, rel
+    tol = 1e-5 if dtype == "c64" else 1e-10
+    assert np.linalg.norm(grad - g_ref) <= tol * max(1e-3, np.linalg.norm(g_ref))
