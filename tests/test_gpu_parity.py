@@ -308,3 +308,31 @@ def test_dense_matrix_gates_forward_and_gradient(P, dtype):
     assert ok, rel
     tol = 1e-5 if dtype == "c64" else 1e-10
     assert np.linalg.norm(grad - g_ref) <= tol * max(1e-3, np.linalg.norm(g_ref))
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("case", ["jw15", "random9-wide"])
+def test_apply_hamiltonian_parity(P, dtype, case):
+    """lambda = H psi through sv_apply_hamiltonian (the adjoint seed) on a
+    dense random state in a permuted layout; the random 9-qubit strings
+    include X/Y supports wider than the local qubits (direct kernel)."""
+    if case == "jw15":
+        n, g, ham = 15, 3, W.jw_terms(15, 200, 501)
+    else:
+        n, g, ham = 9, 1, W.random_pauli(9, 60, 502)
+    v = W.random_state(n, 503, np.complex64 if dtype == "c64" else np.complex128)
+    ref = oracle.hpsi(v.astype(np.complex128), ham)
+    st = P.State(n, g, dtype)
+    out = P.State(n, g, dtype)
+    st.set_amplitudes(v)
+    st.qr_permute([int(x) for x in np.random.default_rng(504).permutation(n)])
+    out.qr_permute(st.layout())
+    _print(f"apply_hamiltonian {case} {dtype}")
+    P.sv_apply_hamiltonian(st.h, P.paulis_array(ham), len(ham.coef), out.h)
+    got = out.get_amplitudes()
+    # each output sums up to n_terms products a_t * psi: the amplitude
+    # tolerance scales with the Hamiltonian's 1-norm
+    assert np.max(np.abs(got - ref)) <= AMP[dtype] * max(1.0, float(np.abs(ham.coef).sum()))
+    assert np.max(np.abs(st.get_amplitudes() - v)) == 0
+    st.close()
+    out.close()
