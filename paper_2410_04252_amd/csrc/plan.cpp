@@ -1078,9 +1078,13 @@ std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched 
             }
             rem.push_back(gi);
         }
-        // level 2: greedy cover of flip masks by k-bit tiles containing the
-        // forced low bits
-        while (!rem.empty()) {
+        // level 2: cover the flip masks by k-bit tiles that contain the forced
+        // low bits.  The groups commute, so any cover is valid: a greedy
+        // (fewest new bits, then most terms, then a fill with the bits most
+        // used by the remaining groups), and the same greedy followed by a
+        // local search that swaps single bits while that covers more groups
+        // in the pass.  The packing with fewer passes is kept.
+        auto cover_pass = [&](const std::vector<int> &rem, bool search) {
             uint64_t S = forced;
             std::vector<char> in(ng, 0);
             while (true) {
@@ -1117,8 +1121,55 @@ std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched 
                 if (bb < 0) break;
                 S |= bit(bb);
             }
-            for (int gi : rem)
-                if (!in[gi] && (px[gi] & ~S) == 0) in[gi] = 1;
+            if (search) {
+                auto covered = [&](uint64_t X) {
+                    int c = 0;
+                    for (int gi : rem) c += (px[gi] & ~X) == 0;
+                    return c;
+                };
+                int cur = covered(S);
+                for (int iter = 0; iter < 64; ++iter) {
+                    int best = cur;
+                    uint64_t bestS = S;
+                    for (uint64_t o = S & ~forced; o; o &= o - 1) {
+                        const uint64_t bo = o & (~o + 1);
+                        for (uint64_t i = localpos & ~S; i; i &= i - 1) {
+                            const uint64_t X = (S & ~bo) | (i & (~i + 1));
+                            const int c = covered(X);
+                            if (c > best) {
+                                best = c;
+                                bestS = X;
+                            }
+                        }
+                    }
+                    if (best <= cur) break;
+                    cur = best;
+                    S = bestS;
+                }
+            }
+            return S;
+        };
+        auto pack = [&](bool search) {
+            std::vector<uint64_t> seq;
+            std::vector<int> r = rem;
+            while (!r.empty()) {
+                const uint64_t S = cover_pass(r, search);
+                std::vector<int> rest;
+                for (int gi : r)
+                    if (px[gi] & ~S) rest.push_back(gi);
+                if (rest.size() == r.size()) break;   // no progress (cannot happen)
+                seq.push_back(S);
+                r.swap(rest);
+            }
+            return seq;
+        };
+        const std::vector<uint64_t> seqA = pack(false), seqB = pack(true);
+        const std::vector<uint64_t> &seqS = seqB.size() < seqA.size() ? seqB : seqA;
+        size_t pass_i = 0;
+        while (!rem.empty() && pass_i < seqS.size()) {
+            const uint64_t S = seqS[pass_i++];
+            std::vector<char> in(ng, 0);
+            for (int gi : rem) in[gi] = (px[gi] & ~S) == 0;
             std::vector<int> pg, rest;
             for (int gi : rem) (in[gi] ? pg : rest).push_back(gi);
             rem.swap(rest);
@@ -1225,6 +1276,7 @@ std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched 
             out.passes.push_back(ea);
             out.hpasses.push_back(ha);
         }
+        if (!rem.empty()) return "internal: Pauli packing left groups uncovered";
         ++qrtile;
     }
     return "";
