@@ -212,3 +212,21 @@ def test_plan_time_is_small(P):
     t2 = time.time()
     assert t1 - t0 < 0.05
     assert t2 - t1 < 5.0
+
+
+@pytest.mark.parametrize("name,n,g,nt,seed", [("jw20", 20, 4, 600, 61), ("jw24", 24, 5, 1500, 62),
+                                              ("rand14", 14, 3, 200, 63)])
+def test_pauli_passes_cover_every_group_once(P, name, n, g, nt, seed):
+    """Level 2 of the Pauli plan (our packing of flip-mask groups into
+    passes) evaluates every group exactly once, in passes whose order never
+    goes back, and every group's flip mask lies in its pass's local set."""
+    ham = W.jw_terms(n, nt, seed) if name.startswith("jw") else W.random_pauli(n, nt, seed)
+    plan = P.sv_plan_paulis(n, g, ham, P.LAZY, 0)
+    groups = list(dict.fromkeys(int(x) for x in ham.x))
+    order = plan["order"]
+    assert sorted(order) == list(range(len(order)))
+    assert len(order) <= len(groups)
+    ps = plan["pass_"]
+    assert all(ps[i] <= ps[i + 1] for i in range(len(ps) - 1))
+    for gi, loc in zip(order, plan["local"]):
+        assert groups[gi] & ~loc == 0
