@@ -86,6 +86,27 @@ __device__ __forceinline__ void shear_rot(R &x, R &y, R t, R s) {
     x = fma_r(-t, y, x);
 }
 
+// Register moves pinned by inline asm.  put_reg writes `val` into the
+// register that already holds `dst`; swap_reg exchanges two registers in
+// place.  The permuting and dense ops end with these, so every op leaves each
+// amplitude in the register that held it before.  Otherwise the op loop's
+// single back edge merges handlers whose results sit in different registers,
+// and register allocation then copies every amplitude after every op.
+__device__ __forceinline__ void put_reg(float &dst, float val) {
+    asm("v_mov_b32 %0, %1" : "+v"(dst) : "v"(val));
+}
+__device__ __forceinline__ void put_reg(double &dst, double val) {
+    asm("v_mov_b64 %0, %1" : "+v"(dst) : "v"(val));
+}
+__device__ __forceinline__ void swap_reg(float &a, float &b) {
+    asm("v_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+}
+__device__ __forceinline__ void swap_reg(double &a, double &b) {
+    const double t = a;
+    put_reg(a, b);
+    put_reg(b, t);
+}
+
 template <int B, typename R, int NR>
 __device__ __forceinline__ void op_diag1(Regs<R, NR> &v, const OpDesc &o) {
     const R t0 = (R)o.m[16], s0 = (R)o.m[17], t1 = (R)o.m[18], s1 = (R)o.m[19];
@@ -133,10 +154,14 @@ __device__ __forceinline__ void op_mix1(Regs<R, NR> &v, const OpDesc &o) {
         if (j & (1 << B)) continue;
         const int j1 = j | (1 << B);
         const R x0r = v.re[j], x0i = v.im[j], x1r = v.re[j1], x1i = v.im[j1];
-        v.re[j] = a_r * x0r - a_i * x0i + b_r * x1r - b_i * x1i;
-        v.im[j] = a_r * x0i + a_i * x0r + b_r * x1i + b_i * x1r;
-        v.re[j1] = c_r * x0r - c_i * x0i + d_r * x1r - d_i * x1i;
-        v.im[j1] = c_r * x0i + c_i * x0r + d_r * x1i + d_i * x1r;
+        const R y0r = a_r * x0r - a_i * x0i + b_r * x1r - b_i * x1i;
+        const R y0i = a_r * x0i + a_i * x0r + b_r * x1i + b_i * x1r;
+        const R y1r = c_r * x0r - c_i * x0i + d_r * x1r - d_i * x1i;
+        const R y1i = c_r * x0i + c_i * x0r + d_r * x1i + d_i * x1r;
+        put_reg(v.re[j], y0r);
+        put_reg(v.im[j], y0i);
+        put_reg(v.re[j1], y1r);
+        put_reg(v.im[j1], y1i);
     }
 }
 
@@ -165,11 +190,8 @@ __device__ __forceinline__ void op_xswap(Regs<R, NR> &v, const OpDesc &) {
     for (int j = 0; j < NR; ++j) {
         if (j & (1 << B)) continue;
         const int j1 = j | (1 << B);
-        const R tr = v.re[j], ti = v.im[j];
-        v.re[j] = v.re[j1];
-        v.im[j] = v.im[j1];
-        v.re[j1] = tr;
-        v.im[j1] = ti;
+        swap_reg(v.re[j], v.re[j1]);
+        swap_reg(v.im[j], v.im[j1]);
     }
 }
 
@@ -179,11 +201,8 @@ __device__ __forceinline__ void op_cnot(Regs<R, NR> &v, const OpDesc &) {
     for (int j = 0; j < NR; ++j) {
         if (!((j >> B0) & 1) || ((j >> B1) & 1)) continue;
         const int j1 = j | (1 << B1);
-        const R tr = v.re[j], ti = v.im[j];
-        v.re[j] = v.re[j1];
-        v.im[j] = v.im[j1];
-        v.re[j1] = tr;
-        v.im[j1] = ti;
+        swap_reg(v.re[j], v.re[j1]);
+        swap_reg(v.im[j], v.im[j1]);
     }
 }
 
@@ -231,6 +250,7 @@ __device__ __forceinline__ void op_mix2(Regs<R, NR> &v, const OpDesc &o) {
             xr[l] = v.re[jl[l]];
             xi[l] = v.im[jl[l]];
         }
+        R yr[4], yi[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             R sr = 0, si = 0;
@@ -239,8 +259,13 @@ __device__ __forceinline__ void op_mix2(Regs<R, NR> &v, const OpDesc &o) {
                 sr += mr[r * 4 + cc] * xr[cc] - mi[r * 4 + cc] * xi[cc];
                 si += mr[r * 4 + cc] * xi[cc] + mi[r * 4 + cc] * xr[cc];
             }
-            v.re[jl[r]] = sr;
-            v.im[jl[r]] = si;
+            yr[r] = sr;
+            yi[r] = si;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            put_reg(v.re[jl[r]], yr[r]);
+            put_reg(v.im[jl[r]], yi[r]);
         }
     }
 }
