@@ -741,6 +741,14 @@ __device__ __forceinline__ void stage_tile(V *lds, const V *__restrict__ src, co
     for (int e = 0; e < E; ++e) lds[tid + NT * e] = x[e];
 }
 
+// v with its sign flipped when bit 0 of par is set (an XOR of the sign bit).
+__device__ __forceinline__ float neg_if_odd(float v, uint32_t par) {
+    return __uint_as_float(__float_as_uint(v) ^ (par << 31));
+}
+__device__ __forceinline__ double neg_if_odd(double v, uint32_t par) {
+    return __longlong_as_double(__double_as_longlong(v) ^ (long long)((uint64_t)par << 63));
+}
+
 template <typename R, int K>
 __global__ __launch_bounds__(1 << evc_tpb(K, sizeof(R) == 8)) void k_evc_pass(
     const typename V2T<R>::type *__restrict__ psi, const EvcPassArgs a,
@@ -767,14 +775,14 @@ __global__ __launch_bounds__(1 << evc_tpb(K, sizeof(R) == 8)) void k_evc_pass(
         const int hb = G.hbit;
         const int need = G.need;
         const int t0 = G.t0, t1 = G.t0 + G.nt;
-        int tb[TPB], wb[Q > 0 ? Q : 1];
-#pragma unroll
-        for (int b = 0; b < TPB; ++b) tb[b] = G.tbits[b];
+        int wb[Q > 0 ? Q : 1];
 #pragma unroll
         for (int b = 0; b < Q; ++b) wb[b] = G.wbits[b];
-        uint32_t tt = 0;
-#pragma unroll
-        for (int b = 0; b < TPB; ++b) tt |= ((threadIdx.x >> b) & 1u) << tb[b];
+        // The thread-index bits are the lowest TPB tile bits other than the
+        // half-space bit hb (the group layout the planner builds), so the
+        // thread's tile index is threadIdx.x with a zero inserted at hb.
+        const uint32_t tid = threadIdx.x;
+        const uint32_t tt = tid + (tid & ~((1u << hb) - 1u));
         uint32_t tt8 = tt * (uint32_t)sizeof(V);
         // keep the byte offset opaque: otherwise (tt8 | wo8) is rewritten as
         // (tt | wo) * 8, one extra shift per LDS address
@@ -834,19 +842,17 @@ __global__ __launch_bounds__(1 << evc_tpb(K, sizeof(R) == 8)) void k_evc_pass(
             for (int u = 0; u < 4; ++u) {
                 const uint32_t wi = (uint32_t)__builtin_amdgcn_readfirstlane(
                     (int)((T[u].zw & (NQ - 1)) | (T[u].use_im ? NQ : 0)));
-                const R val = w[wi];
                 const uint32_t par =
-                    (__builtin_popcount(tt & T[u].zt) + __builtin_popcountll(base & T[u].zg)) & 1u;
-                acc += T[u].coef * (double)(par ? -val : val);
+                    __builtin_popcount(tt & T[u].zt) + __builtin_popcountll(base & T[u].zg);
+                acc += T[u].coef * (double)neg_if_odd(w[wi], par);
             }
         }
         for (; ti < t1; ++ti) {
             const EvcTerm &T = terms[ti];
             const uint32_t wi = (uint32_t)__builtin_amdgcn_readfirstlane(
                 (int)((T.zw & (NQ - 1)) | (T.use_im ? NQ : 0)));
-            const R val = w[wi];
-            const uint32_t par = (__builtin_popcount(tt & T.zt) + __builtin_popcountll(base & T.zg)) & 1u;
-            acc += T.coef * (double)(par ? -val : val);
+            const uint32_t par = __builtin_popcount(tt & T.zt) + __builtin_popcountll(base & T.zg);
+            acc += T.coef * (double)neg_if_odd(w[wi], par);
         }
     }
     const double s = block_sum(acc, red);
