@@ -671,17 +671,25 @@ __global__ __launch_bounds__(256) void k_qr_tiles(V *__restrict__ psi, const QrA
         x[e] = psi[b + off[e]];
         if (pb != b) y[e] = psi[pb + off[e]];
     }
+    // LDS slot of tile element i: the element bits above one bank row
+    // (256 bytes) are folded into the bits below it.  An in-tile transposition
+    // sends neighbouring lanes to elements 2^j apart, which would otherwise
+    // hit the same banks.
+    constexpr int SH = sizeof(V) == 8 ? 5 : 4;
+    auto slot = [](uint32_t i) { return i ^ ((i >> SH) & ((1u << SH) - 1u)); };
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        l0[perm[e]] = x[e];
-        if (pb != b) l1[perm[e]] = y[e];
+        const uint32_t q = slot(perm[e]);
+        l0[q] = x[e];
+        if (pb != b) l1[q] = y[e];
     }
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t t = threadIdx.x + 256u * e;
-        psi[pb + off[e]] = l0[t];
-        if (pb != b) psi[b + off[e]] = l1[t];
+        const uint32_t q = slot(t);
+        psi[pb + off[e]] = l0[q];
+        if (pb != b) psi[b + off[e]] = l1[q];
     }
 }
 
