@@ -1210,8 +1210,16 @@ std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched 
                     else G.wbits[nb - TPB] = b;
                     ++nb;
                 }
+                // The Pauli pass derives a thread's tile index from hbit alone
+                // (its thread index with a zero inserted at hbit), so the
+                // thread-index bits must be the lowest TPB tile bits other
+                // than hbit.
                 uint32_t tmask = 0;
-                for (int j = 0; j < TPB; ++j) tmask |= 1u << G.tbits[j];
+                for (int j = 0; j < TPB; ++j) {
+                    if (G.tbits[j] != j + (j >= G.hbit ? 1 : 0))
+                        return "internal: Pauli group thread bits are not the lowest tile bits";
+                    tmask |= 1u << G.tbits[j];
+                }
                 G.t0 = (int)out.terms.size();
                 G.nt = (int)out.group_terms[gi].size();
                 HpsiGroup HG;
