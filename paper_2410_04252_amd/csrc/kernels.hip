@@ -480,8 +480,12 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
     constexpr int NW = NT / 64;
     constexpr int NWB = K - RB - 6;
     __shared__ V lds[(ADJ ? 2 : 1) << K];
-    const uint32_t tile = blockIdx.x;
-    if (tile >= ntiles) return;
+    if (blockIdx.x >= ntiles) return;
+    // Workgroups are dealt to the 8 XCDs round robin (block b runs on XCD
+    // b mod 8); give each XCD one contiguous eighth of the tiles.  Every tile
+    // of a gate pass does the same work, so no XCD ends up with more.
+    uint32_t tile = blockIdx.x;
+    if ((ntiles & 7u) == 0) tile = (blockIdx.x & 7u) * (ntiles >> 3) + (blockIdx.x >> 3);
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const int np = a.nphase;
     const PhaseDesc &P0 = phases[a.phase0 + (ADJ ? np - 1 : 0)];   // load mapping
