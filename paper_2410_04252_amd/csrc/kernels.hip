@@ -591,27 +591,38 @@ __global__ __launch_bounds__(256) void k_qr_rows(V *__restrict__ psi, const QrAr
     // enumerated as those with h = 0 (the first half), then those with
     // h = l = 1 (a quarter): three quarters of the rows, no wave idle on the
     // (1, 0) quarter.
-    const uint64_t nhalf = a.nrows >> 1, nenum = nhalf + (a.nrows >> 2);
+    // Row indices have n - 6 <= 28 bits, so all index work is 32-bit.
+    const uint32_t nrows = (uint32_t)a.nrows;
+    const uint32_t nhalf = nrows >> 1, nenum = nhalf + (nrows >> 2);
     const int h = a.hbit, l = a.lbit;
-    const uint64_t r0 = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * U;
+    const uint32_t r0 = (blockIdx.x * 4u + (threadIdx.x >> 6)) * U;
     V x[U], y[U];
     uint64_t ra[U], rb[U];
     bool act[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const uint64_t i = r0 + u;
-        uint64_t r;
+        const uint32_t i = r0 + u;
+        uint32_t r;
         if (i < nhalf) {
-            r = ((i >> h) << (h + 1)) | (i & ((1ULL << h) - 1));
+            r = ((i >> h) << (h + 1)) | (i & ((1u << h) - 1u));
         } else {
-            const uint64_t j = i - nhalf;
-            const uint64_t t = ((j >> l) << (l + 1)) | (1ULL << l) | (j & ((1ULL << l) - 1));
-            r = ((t >> h) << (h + 1)) | (1ULL << h) | (t & ((1ULL << h) - 1));
+            const uint32_t j = i - nhalf;
+            const uint32_t t = ((j >> l) << (l + 1)) | (1u << l) | (j & ((1u << l) - 1u));
+            r = ((t >> h) << (h + 1)) | (1u << h) | (t & ((1u << h) - 1u));
         }
-        const uint64_t pr = apply_pairs<32>(r << 6, a.outer, a.nouter) >> 6;
+        // the partner row: every exchanged pair is of physical bits >= 6
+        uint32_t pr = r;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            if (q < a.nouter) {
+                const int pa = a.outer[2 * q] - 6, pb = a.outer[2 * q + 1] - 6;
+                const uint32_t d = ((pr >> pa) ^ (pr >> pb)) & 1u;
+                pr ^= (0u - d) & ((1u << pa) | (1u << pb));
+            }
+        }
         act[u] = i < nenum && r < pr;
-        ra[u] = (r << 6) | lane;
-        rb[u] = (pr << 6) | lane;
+        ra[u] = ((uint64_t)r << 6) | lane;
+        rb[u] = ((uint64_t)pr << 6) | lane;
         if (act[u]) {
             x[u] = psi[ra[u]];
             y[u] = psi[rb[u]];
