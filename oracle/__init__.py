@@ -66,9 +66,9 @@ def lib():
         L.orc_expectation.restype = ctypes.c_double
         L.orc_hpsi.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, up, up, dp]
         L.orc_hpsi.restype = None
-        L.orc_adjoint_grad.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip, ip, dp, ip, ctypes.c_int,
-                                       ctypes.c_int, up, up, dp, dp]
-        L.orc_adjoint_grad.restype = ctypes.c_double
+        L.orc_adjoint_grad.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip, ip, dp, dp, ip, dp,
+                                       ctypes.c_int, ctypes.c_int, up, up, dp, dp, dp]
+        L.orc_adjoint_grad.restype = ctypes.c_int
         L.orc_threads.argtypes = []
         L.orc_threads.restype = ctypes.c_int
         _lib = L
@@ -88,23 +88,36 @@ def _up(a):
 
 
 def _gate_arrays(gates, theta):
-    """(kind, qubits, param[, angle]) -> C arrays (kinds, qs[m*2], angles)."""
+    """Gate tuples -> C arrays (kinds, qs[m*2], angles, params, scales, umats).
+
+    A gate is (kind, qubits, param[, extra[, scale]]): with param >= 0 its
+    angle is scale * theta[param] + extra (extra defaults to 0, scale to 1);
+    with param = -1 the angle is extra (U1/U2: extra is the matrix)."""
     m = len(gates)
     kinds = np.zeros(m, dtype=np.int32)
     qs = np.zeros(2 * m, dtype=np.int32)
     ang = np.zeros(m, dtype=np.float64)
     par = np.full(m, -1, dtype=np.int32)
+    scl = np.ones(m, dtype=np.float64)
+    um = None
     for i, gt in enumerate(gates):
         kind, qub, p = gt[0], gt[1], gt[2]
         kinds[i] = KIND_CODE[kind]
         qs[2 * i] = qub[0]
         qs[2 * i + 1] = qub[1] if len(qub) > 1 else 0
-        if p is not None and p >= 0:
-            ang[i] = theta[p]
+        if kind in ("U1", "U2"):
+            if um is None:
+                um = np.zeros(32 * max(1, m), dtype=np.float64)
+            mat = np.asarray(gt[3], dtype=np.complex128).reshape(-1)
+            um[32 * i:32 * i + 2 * mat.size] = mat.view(np.float64)
+        elif p is not None and p >= 0:
+            off = float(gt[3]) if len(gt) > 3 else 0.0
+            scl[i] = float(gt[4]) if len(gt) > 4 else 1.0
+            ang[i] = scl[i] * theta[p] + off
             par[i] = p
         elif len(gt) > 3:
             ang[i] = gt[3]
-    return kinds, qs, ang, par
+    return kinds, qs, ang, par, scl, um
 
 
 def basis_state(n: int, index: int) -> np.ndarray:
@@ -131,9 +144,9 @@ def apply_circuit(psi: np.ndarray, gates, theta) -> np.ndarray:
     """U_{m-1}...U_0 psi in the given gate order (eq. update_sv_gate)."""
     psi = np.ascontiguousarray(psi, dtype=np.complex128).copy()
     n = int(psi.shape[0]).bit_length() - 1
-    kinds, qs, ang, _ = _gate_arrays(gates, theta)
+    kinds, qs, ang, _, _, um = _gate_arrays(gates, theta)
     rc = lib().orc_apply_circuit(_dp(psi.view(np.float64)), n, len(gates), _ip(kinds), _ip(qs),
-                                 _dp(ang), None)
+                                 _dp(ang), _dp(um) if um is not None else None)
     if rc:
         raise ValueError("bad gate")
     return psi
@@ -143,9 +156,9 @@ def apply_circuit_inplace(psi: np.ndarray, gates, theta) -> None:
     """Like :func:`apply_circuit` but updates ``psi`` (complex128, contiguous)
     in place; used to time the oracle without a full-state copy."""
     n = int(psi.shape[0]).bit_length() - 1
-    kinds, qs, ang, _ = _gate_arrays(gates, theta)
+    kinds, qs, ang, _, _, um = _gate_arrays(gates, theta)
     rc = lib().orc_apply_circuit(_dp(psi.view(np.float64)), n, len(gates), _ip(kinds), _ip(qs),
-                                 _dp(ang), None)
+                                 _dp(ang), _dp(um) if um is not None else None)
     if rc:
         raise ValueError("bad gate")
 
@@ -221,14 +234,19 @@ def adjoint_grad(circ, ham, theta=None):
     """(E, dE/dtheta) by the adjoint recursion (sv_oracle.c: orc_adjoint_grad)."""
     th = np.ascontiguousarray(circ.theta if theta is None else theta, dtype=np.float64)
     psi = basis_state(circ.n, circ.psi0_index)
-    kinds, qs, ang, par = _gate_arrays(circ.gates, th)
+    kinds, qs, ang, par, scl, um = _gate_arrays(circ.gates, th)
     grad = np.zeros(len(th), dtype=np.float64)
-    e = lib().orc_adjoint_grad(_dp(psi.view(np.float64)), circ.n, len(circ.gates), _ip(kinds),
-                               _ip(qs), _dp(ang), _ip(par), len(th), len(ham.coef),
-                               _up(np.ascontiguousarray(ham.x, dtype=np.uint64)),
-                               _up(np.ascontiguousarray(ham.z, dtype=np.uint64)),
-                               _dp(np.ascontiguousarray(ham.coef, dtype=np.float64)), _dp(grad))
-    return e, grad
+    e = np.zeros(1, dtype=np.float64)
+    rc = lib().orc_adjoint_grad(_dp(psi.view(np.float64)), circ.n, len(circ.gates), _ip(kinds),
+                                _ip(qs), _dp(ang), _dp(um) if um is not None else None, _ip(par),
+                                _dp(scl), len(th), len(ham.coef),
+                                _up(np.ascontiguousarray(ham.x, dtype=np.uint64)),
+                                _up(np.ascontiguousarray(ham.z, dtype=np.uint64)),
+                                _dp(np.ascontiguousarray(ham.coef, dtype=np.float64)), _dp(grad),
+                                _dp(e))
+    if rc:
+        raise ValueError(f"oracle adjoint failed ({rc})")
+    return float(e[0]), grad
 
 
 def fd_grad(circ, ham, params=None, h: float = 1e-4):
@@ -258,9 +276,23 @@ SHIFT_RULES = {
 }
 
 
-def param_shift_grad(circ, ham, params=None):
-    """Exact parameter-shift gradient; a parameter shared by several gates is
-    differentiated gate by gate (product rule)."""
+# The two-term rule applied to every gate whatever its spectrum: exact for
+# one-frequency gates only (the nominal two evaluations per parameter).
+TWO_TERM_RULE = ((math.pi / 2, 0.5),)
+
+
+def _gate_angle(gt, th):
+    p = gt[2]
+    off = float(gt[3]) if len(gt) > 3 else 0.0
+    scl = float(gt[4]) if len(gt) > 4 else 1.0
+    return scl * th[p] + off, scl
+
+
+def param_shift_grad(circ, ham, params=None, rule="exact"):
+    """Parameter-shift gradient.  A parameter shared by several gates is
+    differentiated gate by gate (product rule), each gate's derivative times
+    its angle scale (chain rule).  rule="exact" uses SHIFT_RULES;
+    rule="two-term" uses TWO_TERM_RULE for every gate."""
     th = np.array(circ.theta, dtype=np.float64)
     idx = range(len(th)) if params is None else params
     out = []
@@ -269,15 +301,17 @@ def param_shift_grad(circ, ham, params=None):
         for gi, gt in enumerate(circ.gates):
             if gt[2] != p:
                 continue
-            for shift, w in SHIFT_RULES[gt[0]]:
+            ang, scl = _gate_angle(gt, th)
+            rules = SHIFT_RULES[gt[0]] if rule == "exact" else TWO_TERM_RULE
+            for shift, w in rules:
                 vals = []
                 for sgn in (+1, -1):
                     gates = list(circ.gates)
                     # shift only this gate: give it a private fixed angle
-                    gates[gi] = (gt[0], gt[1], -1, th[p] + sgn * shift)
+                    gates[gi] = (gt[0], gt[1], -1, ang + sgn * shift)
                     psi = apply_circuit(basis_state(circ.n, circ.psi0_index), gates, th)
                     vals.append(expectation(psi, ham))
-                acc += w * (vals[0] - vals[1])
+                acc += scl * w * (vals[0] - vals[1])
         out.append(acc)
     return np.array(out)
 

@@ -88,11 +88,21 @@ def embed(n: int, local: np.ndarray, qubits) -> np.ndarray:
 
 
 def circuit_unitary(n: int, gates, theta) -> np.ndarray:
+    """Product of the embedded gate matrices.  A parametric gate's angle is
+    scale * theta[param] + offset (gate tuple entries 4 and 3, defaults 1 and
+    0); U1/U2 gates carry their matrix as entry 3."""
     U = np.eye(1 << n, dtype=np.complex128)
     for gt in gates:
         kind, qubits, p = gt[0], gt[1], gt[2]
-        ang = theta[p] if p is not None and p >= 0 else (gt[3] if len(gt) > 3 else 0.0)
-        U = embed(n, gate(kind, ang), qubits) @ U
+        if kind in ("U1", "U2"):
+            local = np.asarray(gt[3], dtype=np.complex128).reshape(2 * len(qubits), -1)
+        else:
+            if p is not None and p >= 0:
+                ang = (gt[4] if len(gt) > 4 else 1.0) * theta[p] + (gt[3] if len(gt) > 3 else 0.0)
+            else:
+                ang = gt[3] if len(gt) > 3 else 0.0
+            local = gate(kind, ang)
+        U = embed(n, local, qubits) @ U
     return U
 
 

@@ -289,44 +289,54 @@ static cplx inner(const cplx *a, const cplx *b, int64_t N) {
 }
 
 /* Adjoint-method gradient of E(theta) = <psi0|U^dag H U|psi0>.
- * psi_ri holds psi0 on entry and U psi0 on exit.  gate_param[i] is the theta
- * index of gate i (-1: fixed).  grad[n_theta] is overwritten.
+ * psi_ri holds psi0 on entry and U psi0 on exit.  angles[i] is gate i's
+ * angle, umats[i*32..] its U1/U2 matrix (NULL when no gate is dense),
+ * gate_param[i] the theta index the angle depends on (-1: fixed) and
+ * gate_scale[i] = d(angle_i)/d(theta[gate_param[i]]).  grad[n_theta] is
+ * overwritten, *energy_out receives E.  Returns 0, or -1 on a bad gate.
  *
  * With psi_j = U_j ... U_0 psi0 and lambda_j = U_{j+1}^dag ... U_{m-1}^dag H psi_{m-1}:
- * dE/dt_j = 2 Re <lambda_j| dU_j/dt |psi_{j-1}> = 2 Im <lambda_j| K_j |psi_j>
- * because dU/dt = -i K U for U = exp(-i t K).  Walk j = m-1 .. 0, evaluating
- * the term, then psi <- U_j^dag psi, lambda <- U_j^dag lambda.  Returns E. */
-double orc_adjoint_grad(double *psi_ri, int n, int m, const int *kinds, const int *qs,
-                        const double *angles, const int *gate_param, int n_theta,
-                        int nt, const uint64_t *xs, const uint64_t *zs, const double *coef,
-                        double *grad) {
+ * dE/da_j = 2 Re <lambda_j| dU_j/da |psi_{j-1}> = 2 Im <lambda_j| K_j |psi_j>
+ * because dU/da = -i K U for U = exp(-i a K); the chain rule multiplies by
+ * gate_scale[j].  Walk j = m-1 .. 0, evaluating the term, then
+ * psi <- U_j^dag psi, lambda <- U_j^dag lambda. */
+int orc_adjoint_grad(double *psi_ri, int n, int m, const int *kinds, const int *qs,
+                     const double *angles, const double *umats, const int *gate_param,
+                     const double *gate_scale, int n_theta, int nt, const uint64_t *xs,
+                     const uint64_t *zs, const double *coef, double *grad, double *energy_out) {
     const int64_t N = (int64_t)1 << n;
     cplx *psi = (cplx *)psi_ri;
+    int rc = orc_apply_circuit(psi_ri, n, m, kinds, qs, angles, umats);
+    if (rc) return rc;
     cplx *lam = (cplx *)malloc(sizeof(cplx) * (size_t)N);
     cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)N);
-    for (int i = 0; i < m; ++i)
-        orc_apply_gate(psi_ri, n, kinds[i], qs + 2 * i, angles[i], NULL, 0);
-    orc_hpsi((double *)lam, psi_ri, n, nt, xs, zs, coef);
-    double E = creal(inner(psi, lam, N));
-    /* keep U psi0 for the caller */
     cplx *keep = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    if (!lam || !tmp || !keep) {
+        free(lam); free(tmp); free(keep);
+        return -2;
+    }
+    orc_hpsi((double *)lam, psi_ri, n, nt, xs, zs, coef);
+    *energy_out = creal(inner(psi, lam, N));
+    /* keep U psi0 for the caller */
     memcpy(keep, psi, sizeof(cplx) * (size_t)N);
     for (int t = 0; t < n_theta; ++t) grad[t] = 0.0;
-    for (int i = m - 1; i >= 0; --i) {
+    for (int i = m - 1; i >= 0 && rc == 0; --i) {
+        const double *um = umats ? umats + 32 * i : NULL;
         if (gate_param[i] >= 0) {
             memcpy(tmp, psi, sizeof(cplx) * (size_t)N);
-            orc_apply_generator((double *)tmp, n, kinds[i], qs + 2 * i);
+            rc = orc_apply_generator((double *)tmp, n, kinds[i], qs + 2 * i);
+            if (rc) break;
             cplx v = inner(lam, tmp, N);
-            grad[gate_param[i]] += 2.0 * cimag(v);
+            grad[gate_param[i]] += gate_scale[i] * 2.0 * cimag(v);
         }
-        orc_apply_gate(psi_ri, n, kinds[i], qs + 2 * i, angles[i], NULL, 1);
-        orc_apply_gate((double *)lam, n, kinds[i], qs + 2 * i, angles[i], NULL, 1);
+        rc = orc_apply_gate(psi_ri, n, kinds[i], qs + 2 * i, angles[i], um, 1);
+        if (rc == 0) rc = orc_apply_gate((double *)lam, n, kinds[i], qs + 2 * i, angles[i], um, 1);
     }
     memcpy(psi, keep, sizeof(cplx) * (size_t)N);
     free(keep);
     free(tmp);
     free(lam);
-    return E;
+    return rc;
 }
 
 /* OpenMP threads used by the parallel loops above. */

@@ -304,3 +304,77 @@ def test_givens_two_frequency_shift_rule():
     two_term = 0.5 * (oracle.energy(c, h, np.array([0.7, 1.9, 0.4 + math.pi / 2]))
                       - oracle.energy(c, h, np.array([0.7, 1.9, 0.4 - math.pi / 2])))
     assert abs(two_term - gf) > 1e-3
+
+
+def _haar(rng, d):
+    z = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def test_adjoint_with_dense_gates_vs_fd_and_kron():
+    """Circuits with fixed U1/U2 matrices between parametric gates: the
+    adjoint recursion (which applies the matrices' conjugate transposes) equals
+    central finite differences, and the final state equals the Kronecker
+    product of the gate matrices."""
+    rng = np.random.default_rng(606)
+    n = 5
+    gates, p = [], 0
+    for layer in range(2):
+        gates.append(("U2", (layer, 3), -1, _haar(rng, 4)))
+        for q in range(n):
+            gates.append(("U1", (q,), -1, _haar(rng, 2)))
+            gates.append(("RY", (q,), p)); p += 1
+        gates.append(("GIVENS", (1, 4), p)); p += 1
+        gates.append(("CPHASE", (0, 2), p)); p += 1
+    c = W.Circuit(n, gates, rng.uniform(-math.pi, math.pi, size=p), 3)
+    h = W.random_pauli(n, 12, 607)
+    e, ga = oracle.adjoint_grad(c, h)
+    assert abs(e - oracle.energy(c, h)) < 1e-12
+    np.testing.assert_allclose(ga, oracle.fd_grad(c, h), atol=1e-7)
+    np.testing.assert_allclose(ga, oracle.param_shift_grad(c, h), atol=1e-11)
+    U = brute.circuit_unitary(n, c.gates, c.theta)
+    np.testing.assert_allclose(oracle.run_circuit(c), U[:, 3], atol=1e-12)
+
+
+def test_scaled_shared_parameter_chain_rule():
+    """A parameter read by two gates through angle = scale * theta + offset:
+    the oracle's adjoint (chain rule per gate) equals central finite
+    differences of the energy in theta and the closed form of the two-gate
+    product RY(a1 t + b1) RY(a2 t + b2)|0> with H = Z: E = cos(sum of angles)."""
+    for a1, b1, a2, b2, t in ((0.5, 0.3, -2.0, 0.1, 0.7), (3.0, -1.0, 1.5, 0.0, -0.4)):
+        c = W.Circuit(1, [("RY", (0,), 0, b1, a1), ("RY", (0,), 0, b2, a2)], np.array([t]), 0)
+        h = W.Hamiltonian(1, np.array([0], dtype=np.uint64), np.array([1], dtype=np.uint64),
+                          np.array([1.0]))
+        e, g = oracle.adjoint_grad(c, h)
+        ang = a1 * t + b1 + a2 * t + b2
+        assert abs(e - math.cos(ang)) < 1e-14
+        assert abs(g[0] + (a1 + a2) * math.sin(ang)) < 1e-13
+        assert abs(oracle.fd_grad(c, h)[0] - g[0]) < 1e-7
+        assert abs(oracle.param_shift_grad(c, h)[0] - g[0]) < 1e-13
+    # on a fabric circuit with every angle scaled and shifted, parameters shared
+    rng = np.random.default_rng(608)
+    base = W.fabric(8, 4, 609)
+    gates = [(k, q, p % 5, float(rng.uniform(-1, 1)), float(rng.choice([-2.0, 0.5, 1.5])))
+             for k, q, p in base.gates]
+    c = W.Circuit(8, gates, rng.uniform(-math.pi, math.pi, size=5), base.psi0_index)
+    h = W.jw_terms(8, 40, 610)
+    _, ga = oracle.adjoint_grad(c, h)
+    np.testing.assert_allclose(ga, oracle.fd_grad(c, h), atol=1e-7)
+    np.testing.assert_allclose(ga, oracle.param_shift_grad(c, h), atol=1e-11)
+
+
+def test_two_term_rule_exact_for_one_frequency_gates_only():
+    """The nominal two-evaluation rule equals the exact gradient for RY/RZ/
+    CPHASE parameters and differs for GIVENS ones."""
+    c = W.fabric(6, 2, 611)
+    h = W.jw_terms(6, 30, 612)
+    g_exact = oracle.param_shift_grad(c, h)
+    g_two = oracle.param_shift_grad(c, h, rule="two-term")
+    gf = oracle.fd_grad(c, h)
+    np.testing.assert_allclose(g_exact, gf, atol=1e-7)
+    for kind, _, p in c.gates:
+        if kind == "CPHASE":
+            assert abs(g_two[p] - gf[p]) < 1e-7
+    giv = [p for kind, _, p in c.gates if kind == "GIVENS"]
+    assert max(abs(g_two[p] - gf[p]) for p in giv) > 1e-4
