@@ -275,7 +275,7 @@ def measure_grad(P, W, torch, args):
     cfg = W.config("grad24")
     circ, ham = cfg["circuit"], cfg["ham"]
     n = circ.n
-    g = 5
+    g = cfg["g"]
     st = P.State(n, g, "c64")
     h = st.h
     gates_c = P.gates_array(circ.gates)

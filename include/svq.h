@@ -49,7 +49,10 @@ typedef enum { SVQ_EAGER = 0, SVQ_LAZY = 1 } svq_sched;
 typedef enum {
     SVQ_OK = 0,
     SVQ_EINVAL = -1,     /* bad argument; the handle is unchanged */
-    SVQ_ENOMEM = -2,     /* device or host allocation failed */
+    SVQ_ENOMEM = -2,     /* a device allocation failed (or exceeded the optional
+                            cap SVQ_MAX_ALLOC_BYTES, in bytes, read from the
+                            environment); scratch is allocated before any
+                            launch, so the handle is unchanged and usable */
     SVQ_EHIP = -3,       /* a HIP call failed; the handle is poisoned */
     SVQ_ESHAPE = -4,     /* sizes inconsistent (buffer too small, n out of range) */
     SVQ_EUNSUP = -5,     /* valid but not supported by this library */
@@ -70,14 +73,17 @@ typedef enum {
 
 /* One gate.  The gate's matrix uses local index l = sum_j bit_{q[j]} 2^j, so
  * q[0] is the low bit (the paper leaves the order open).  The angle is
- * theta[param] when param >= 0, else `angle`.  Parametric kinds follow
- * U(t) = exp(-i t K): RX/RY/RZ K = sigma/2; CPHASE K = -|11><11|;
- * GIVENS K = (X_q0 Y_q1 - Y_q0 X_q1)/4. */
+ * scale * theta[param] + offset when param >= 0, else offset, so one
+ * parameter may drive several gates through different affine maps (sv_grad
+ * applies the chain rule).  Parametric kinds follow U(t) = exp(-i t K):
+ * RX/RY/RZ K = sigma/2; CPHASE K = -|11><11|; GIVENS K = (X_q0 Y_q1 -
+ * Y_q0 X_q1)/4.  scale and offset must be finite. */
 typedef struct {
     int32_t kind;
     int32_t q[2];
-    int32_t param;
-    double angle;
+    int32_t param;     /* index into theta[], or -1 for a fixed angle */
+    double scale;      /* d angle / d theta[param] (ignored when param < 0) */
+    double offset;     /* added to the angle; the whole angle when param < 0 */
     double mat[32];    /* U1: 2x2, U2: 4x4, row-major complex as (re, im) */
 } svq_gate;
 
@@ -121,6 +127,17 @@ svq_status sv_set_amplitudes(svq_state st, const void *host_logical);
 /* Copy the state to a host array in logical order.  May reorder the device
  * buffer back to the identity layout first (the logical state is kept). */
 svq_status sv_get_amplitudes(svq_state st, void *host_logical);
+
+/* The last plan this handle executed (sv_apply_circuit, sv_expectation,
+ * sv_grad's circuit plan) as JSON text, for inspection and tests: schedule,
+ * tile width k, low bits c, QR count (eq. n_qr), the schedule order, and the
+ * steps in launch order -- {"type":"qr","swaps":[[a,b],...]} with physical bit
+ * pairs, {"type":"gate_pass","tile_bits":[...],"gates":G,"phases":F} or
+ * {"type":"pauli_pass","tile_bits":[...],"groups":X} -- plus the layouts
+ * before and after.  "{}" before any plan ran.  *len_out (nullable) receives
+ * the size including the terminating NUL; json_buf may be NULL to query it.
+ * Errors: EINVAL (null handle), ESHAPE (cap too small; nothing written). */
+svq_status sv_plan_dump(svq_state st, char *json_buf, size_t cap, size_t *len_out);
 
 /* Physical position of every logical qubit (pos_out[n]). */
 svq_status sv_get_layout(svq_state st, int32_t *pos_out);
@@ -175,11 +192,19 @@ svq_status sv_apply_hamiltonian(svq_state st, const svq_pauli *terms, int n_term
                                 svq_state out);
 
 /* Gradient of E(theta) = <psi0|U(theta)^dag H U(theta)|psi0> by the adjoint
- * method: forward pass, lambda = H psi, then a reverse sweep that un-applies
- * every gate on psi and lambda (no per-layer checkpoints) while summing
- * dE/dt_j = 2 Im <lambda|K_j|psi> in FP64.  The handle's current state is
- * psi0; on return it holds U(theta)psi0.  grad_host/grad_dev receive n_theta
- * doubles, energy_host/energy_dev E.  Errors: as sv_apply_circuit. */
+ * method (objective eq. vqe): forward pass, lambda = H psi, then a reverse
+ * sweep that un-applies every gate on psi and lambda (no per-layer
+ * checkpoints: one forward and one adjoint state) while summing
+ * dE/dtheta_p = sum over the gates j of p of scale_j * 2 Im <lambda|K_j|psi>
+ * (FP64 per-block partials, then a deterministic FP64 reduction).  The
+ * handle's current state is psi0.  The reverse sweep recomputes psi0 from
+ * U(theta)psi0, so on return the handle holds psi0 again (equal to the input
+ * up to rounding: about 1e-7 per call in complex64), in its original layout,
+ * ready for the next parameter vector; U(theta)psi0 itself is not kept (it
+ * would cost a third state or a second forward pass).  grad_host/grad_dev
+ * receive n_theta doubles, energy_host/energy_dev E.  Scratch: lambda (one
+ * state) plus (parametric gates of the largest pass) x 2^(n - k) doubles.
+ * Errors: as sv_apply_circuit. */
 svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *theta,
                    int n_theta, const svq_pauli *terms, int n_terms, svq_sched sched,
                    double *energy_host, double *energy_dev, double *grad_host,

@@ -27,7 +27,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESHAPE", -5: "EU
 
 class svq_gate(ctypes.Structure):
     _fields_ = [("kind", c_int32), ("q", c_int32 * 2), ("param", c_int32),
-                ("angle", c_double), ("mat", c_double * 32)]
+                ("scale", c_double), ("offset", c_double), ("mat", c_double * 32)]
 
 
 class svq_pauli(ctypes.Structure):
@@ -50,7 +50,7 @@ class SvqError(RuntimeError):
 
 
 EXPORTS = ("sv_create", "sv_destroy", "sv_set_basis", "sv_set_amplitudes", "sv_get_amplitudes",
-           "sv_get_layout", "sv_device_ptr", "sv_apply_circuit", "sv_qr_permute",
+           "sv_get_layout", "sv_plan_dump", "sv_device_ptr", "sv_apply_circuit", "sv_qr_permute",
            "sv_expectation", "sv_expectation_qsu", "sv_apply_hamiltonian", "sv_grad", "sv_plan_circuit",
            "sv_plan_paulis", "sv_plan_ops", "sv_tune_circuit", "sv_tune_paulis",
            "sv_batch_tune", "sv_tune_save", "sv_tune_load", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
@@ -70,6 +70,7 @@ def _load():
     L.sv_get_amplitudes.argtypes = [vp, vp]
     L.sv_get_layout.argtypes = [vp, POINTER(c_int32)]
     L.sv_device_ptr.argtypes = [vp, POINTER(vp)]
+    L.sv_plan_dump.argtypes = [vp, ctypes.c_char_p, c_size_t, POINTER(c_size_t)]
     L.sv_apply_circuit.argtypes = [vp, POINTER(svq_gate), c_int, POINTER(c_double), c_int, c_int,
                                    c_int, POINTER(svq_stats)]
     L.sv_qr_permute.argtypes = [vp, POINTER(c_int32)]
@@ -128,7 +129,11 @@ def _check(rc):
 # ---------------------------------------------------------------------------
 
 def gates_array(gates):
-    """[(kind, qubits, param[, angle or matrix])] -> ctypes svq_gate array."""
+    """[(kind, qubits, param[, extra[, scale]])] -> ctypes svq_gate array.
+
+    With param >= 0 the angle is scale * theta[param] + extra (extra defaults
+    to 0, scale to 1); with param = -1 it is extra.  For U1/U2, extra is the
+    matrix."""
     arr = (svq_gate * max(1, len(gates)))()
     for i, gt in enumerate(gates):
         kind, qs, p = gt[0], gt[1], gt[2]
@@ -137,6 +142,7 @@ def gates_array(gates):
         g.q[0] = int(qs[0])
         g.q[1] = int(qs[1]) if len(qs) > 1 else 0
         g.param = int(p) if p is not None and p >= 0 else -1
+        g.scale = float(gt[4]) if len(gt) > 4 else 1.0
         if len(gt) > 3:
             extra = gt[3]
             if kind in ("U1", "U2"):
@@ -144,7 +150,7 @@ def gates_array(gates):
                 for j, v in enumerate(m):
                     g.mat[j] = float(v)
             else:
-                g.angle = float(extra)
+                g.offset = float(extra)
     return arr
 
 
@@ -200,6 +206,16 @@ def sv_get_layout(h, n):
     out = (c_int32 * n)()
     _check(lib.sv_get_layout(h, out))
     return list(out)
+
+
+def sv_plan_dump(h):
+    """The handle's last executed plan, parsed from the library's JSON."""
+    import json
+    need = c_size_t(0)
+    _check(lib.sv_plan_dump(h, None, 0, byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib.sv_plan_dump(h, buf, need.value, None))
+    return json.loads(buf.value.decode())
 
 
 def sv_device_ptr(h):
@@ -397,6 +413,9 @@ class State:
 
     def layout(self):
         return sv_get_layout(self.h, self.n)
+
+    def plan_dump(self):
+        return sv_plan_dump(self.h)
 
     def apply(self, circuit, theta=None, sched=LAZY, tile_k=0):
         gc = gates_array(circuit.gates)

@@ -28,6 +28,15 @@ svq_status fail(svq_status s, const std::string &msg) {
     return s;
 }
 
+// Largest single device allocation the library makes (SVQ_MAX_ALLOC_BYTES,
+// default unlimited); a larger request fails as out of memory, which lets the
+// ENOMEM paths be exercised without exhausting the device.
+size_t alloc_cap() {
+    const char *v = std::getenv("SVQ_MAX_ALLOC_BYTES");
+    if (!v || !*v) return SIZE_MAX;
+    return (size_t)std::strtoull(v, nullptr, 10);
+}
+
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
@@ -36,6 +45,7 @@ struct DevBuf {
     }
     hipError_t ensure(size_t bytes) {
         if (bytes <= cap) return hipSuccess;
+        if (std::max<size_t>(bytes, 256) > alloc_cap()) return hipErrorOutOfMemory;
         if (p) {
             (void)hipFree(p);
             p = nullptr;
@@ -51,15 +61,102 @@ struct DevBuf {
 struct CachedCircuit {
     CircuitPlan plan;
     DevBuf d_phases;
-    bool uploaded = false;
+    std::shared_ptr<const std::string> json;   // sv_plan_dump text
 };
 
 struct CachedPaulis {
     PauliPlan plan;
     std::vector<WideTerm> wide;
     DevBuf d_groups, d_terms, d_hgroups, d_hterms, d_off, d_nblk, d_wide;
-    bool uploaded = false;
+    std::shared_ptr<const std::string> json;
 };
+
+// ---- sv_plan_dump: the executed steps of a plan as JSON ----------------------
+
+void json_qr(std::string &o, const std::vector<Transposition> &tr) {
+    o += "{\"type\":\"qr\",\"swaps\":[";
+    for (size_t i = 0; i < tr.size(); ++i) {
+        if (i) o += ",";
+        o += "[" + std::to_string(tr[i].a) + "," + std::to_string(tr[i].b) + "]";
+    }
+    o += "]}";
+}
+
+void json_bits(std::string &o, const int8_t *bits, int nb) {
+    o += "[";
+    for (int j = 0; j < nb; ++j) {
+        if (j) o += ",";
+        o += std::to_string((int)bits[j]);
+    }
+    o += "]";
+}
+
+std::string circuit_json(const CircuitPlan &P, svq_sched sched, bool adj) {
+    std::vector<int> gates_in_pass(P.passes.size(), 0);
+    for (int p : P.pos_pass) gates_in_pass[p]++;
+    std::string o = "{\"kind\":\"circuit\",\"schedule\":\"";
+    o += sched == SVQ_LAZY ? "lazy" : "eager";
+    o += "\",\"adjoint\":" + std::string(adj ? "true" : "false");
+    o += ",\"n\":" + std::to_string(P.n) + ",\"g\":" + std::to_string(P.g);
+    o += ",\"tile_k\":" + std::to_string(P.k) + ",\"low_bits\":" + std::to_string(P.c);
+    o += ",\"reg_bits\":" + std::to_string(P.rb) + ",\"n_qr\":" + std::to_string(P.n_qr);
+    o += ",\"n_passes\":" + std::to_string(P.passes.size());
+    o += ",\"order\":[";
+    for (size_t i = 0; i < P.order.size(); ++i) o += (i ? "," : "") + std::to_string(P.order[i]);
+    o += "],\"steps\":[";
+    bool first = true;
+    for (const Step &s : P.steps) {
+        if (!first) o += ",";
+        first = false;
+        if (s.type == 0) {
+            json_qr(o, s.qr);
+            continue;
+        }
+        const PassArgs &a = P.passes[s.idx];
+        o += "{\"type\":\"gate_pass\",\"pass\":" + std::to_string(s.idx) + ",\"tile_bits\":";
+        json_bits(o, a.tphys, P.k);
+        o += ",\"gates\":" + std::to_string(gates_in_pass[s.idx]);
+        o += ",\"phases\":" + std::to_string(a.nphase) + "}";
+    }
+    o += "],\"pos_before\":[";
+    for (size_t q = 0; q < P.pos_before.size(); ++q) o += (q ? "," : "") + std::to_string(P.pos_before[q]);
+    o += "],\"pos_after\":[";
+    for (size_t q = 0; q < P.pos_after.size(); ++q) o += (q ? "," : "") + std::to_string(P.pos_after[q]);
+    o += "]}";
+    return o;
+}
+
+std::string pauli_json(const PauliPlan &P, svq_sched sched) {
+    std::string o = "{\"kind\":\"paulis\",\"schedule\":\"";
+    o += sched == SVQ_LAZY ? "lazy" : "eager";
+    o += "\",\"n\":" + std::to_string(P.n) + ",\"g\":" + std::to_string(P.g);
+    o += ",\"tile_k\":" + std::to_string(P.k) + ",\"low_bits\":" + std::to_string(P.c);
+    o += ",\"n_qr\":" + std::to_string(P.n_qr) + ",\"n_groups\":" + std::to_string(P.group_x.size());
+    o += ",\"n_passes\":" + std::to_string(P.passes.size());
+    o += ",\"wide_groups\":" + std::to_string(P.wide_groups.size());
+    o += ",\"group_order\":[";
+    for (size_t i = 0; i < P.order.size(); ++i) o += (i ? "," : "") + std::to_string(P.order[i]);
+    o += "],\"steps\":[";
+    bool first = true;
+    for (const Step &s : P.steps) {
+        if (!first) o += ",";
+        first = false;
+        if (s.type == 0) {
+            json_qr(o, s.qr);
+            continue;
+        }
+        const EvcPassArgs &a = P.passes[s.idx];
+        o += "{\"type\":\"pauli_pass\",\"pass\":" + std::to_string(s.idx) + ",\"tile_bits\":";
+        json_bits(o, a.tphys, P.k);
+        o += ",\"groups\":" + std::to_string(a.ngroups) + "}";
+    }
+    o += "],\"pos_before\":[";
+    for (size_t q = 0; q < P.pos_before.size(); ++q) o += (q ? "," : "") + std::to_string(P.pos_before[q]);
+    o += "],\"pos_after\":[";
+    for (size_t q = 0; q < P.pos_after.size(); ++q) o += (q ? "," : "") + std::to_string(P.pos_after[q]);
+    o += "]}";
+    return o;
+}
 
 int env_int(const char *name, int dflt) {
     const char *v = std::getenv(name);
@@ -79,7 +176,9 @@ struct svq_state_s {
     bool poisoned = false;
     std::map<std::string, std::unique_ptr<CachedCircuit>> ccache;
     std::map<std::string, std::unique_ptr<CachedPaulis>> pcache;
-    DevBuf d_ops, d_partials, d_chunks, d_extra, d_lam, d_gpart, d_pptr, d_pgate, d_energy, d_grad;
+    std::shared_ptr<const std::string> last_plan;   // JSON of the last executed plan
+    DevBuf d_ops, d_partials, d_chunks, d_extra, d_lam, d_gpart, d_gop, d_ggates, d_pptr, d_pgate,
+        d_energy, d_grad;
     int device = 0;
     // per-launch event timing (sv_profile)
     bool prof = false;
@@ -126,7 +225,11 @@ struct ProfScope {
     }
 };
 
+// A failed device allocation is ENOMEM and leaves the handle usable: every
+// entry point allocates its scratch before its first launch.  Any other HIP
+// failure poisons the handle.
 svq_status hip_fail(svq_state st, hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory) return fail(SVQ_ENOMEM, std::string(what) + ": out of device memory");
     if (st) st->poisoned = true;
     return fail(SVQ_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -383,6 +486,7 @@ svq_status get_circuit_plan(svq_state st, const std::vector<GateN> &gates, svq_s
     if (!err.empty()) return fail(SVQ_EINVAL, err);
     auto t1 = std::chrono::steady_clock::now();
     *ms_plan = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    cc->json = std::make_shared<const std::string>(circuit_json(cc->plan, sched, adj));
     HIPCHK(st, cc->d_phases.ensure(sizeof(PhaseDesc) * std::max<size_t>(1, cc->plan.phases.size())),
            "alloc phases");
     HIPCHK(st, hipMemcpyAsync(cc->d_phases.p, cc->plan.phases.data(),
@@ -415,6 +519,7 @@ svq_status check_theta(const std::vector<GateN> &gates, const double *theta, int
 svq_status run_circuit(svq_state st, CachedCircuit *cc, const std::vector<GateN> &gates,
                        const double *theta, svq_stats *stats) {
     CircuitPlan &P = cc->plan;
+    st->last_plan = cc->json;
     std::vector<OpDesc> ops = P.ops;
     fill_ops(gates, theta, P.op_gate, ops, false);
     HIPCHK(st, st->d_ops.ensure(sizeof(OpDesc) * std::max<size_t>(1, ops.size())), "alloc ops");
@@ -494,6 +599,7 @@ svq_status get_pauli_plan(svq_state st, const svq_pauli *terms, int nt, svq_sche
         }
     auto t1 = std::chrono::steady_clock::now();
     *ms_plan = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    cp->json = std::make_shared<const std::string>(pauli_json(P, sched));
     auto up = [&](DevBuf &b, const void *src, size_t nb) -> hipError_t {
         hipError_t e = b.ensure(std::max<size_t>(nb, 64));
         if (e != hipSuccess) return e;
@@ -523,6 +629,7 @@ svq_status get_pauli_plan(svq_state st, const svq_pauli *terms, int nt, svq_sche
 svq_status run_expectation(svq_state st, CachedPaulis *cp, double *energy_dev, double *chunk_dev,
                            svq_stats *stats) {
     PauliPlan &P = cp->plan;
+    st->last_plan = cp->json;
     const int nchunk = 1 << st->g;
     HIPCHK(st, st->d_partials.ensure(sizeof(double) * std::max(1, P.total_blocks)), "alloc partials");
     HIPCHK(st, st->d_chunks.ensure(sizeof(double) * (nchunk + reduce_scratch(nchunk))), "alloc chunks");
@@ -624,6 +731,7 @@ svq_status sv_create(int n, int g, svq_dtype dtype, void *dev_buf, size_t buf_by
         st->buf = dev_buf;
         st->owns = false;
     } else {
+        if (st->bytes() > alloc_cap()) return fail(SVQ_ENOMEM, "state larger than SVQ_MAX_ALLOC_BYTES");
         e = hipMalloc(&st->buf, st->bytes());
         if (e != hipSuccess) return fail(SVQ_ENOMEM, std::string("hipMalloc state: ") + hipGetErrorString(e));
         st->owns = true;
@@ -675,6 +783,17 @@ svq_status sv_get_amplitudes(svq_state st, void *host) {
     if (s) return s;
     HIPCHK(st, hipMemcpyAsync(host, st->buf, st->bytes(), hipMemcpyDeviceToHost, st->stream), "D2H");
     HIPCHK(st, hipStreamSynchronize(st->stream), "sync");
+    return SVQ_OK;
+}
+
+svq_status sv_plan_dump(svq_state st, char *json_buf, size_t cap, size_t *len_out) {
+    if (!st) return fail(SVQ_EINVAL, "null handle");
+    const std::string empty = "{}";
+    const std::string &j = st->last_plan ? *st->last_plan : empty;
+    if (len_out) *len_out = j.size() + 1;
+    if (!json_buf) return SVQ_OK;
+    if (cap < j.size() + 1) return fail(SVQ_ESHAPE, "json_buf smaller than the plan text");
+    std::memcpy(json_buf, j.c_str(), j.size() + 1);
     return SVQ_OK;
 }
 
@@ -821,38 +940,19 @@ svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *the
     s = get_circuit_plan(st, gn, sched, k, true, &cc, &ms);
     if (s) return s;
     CircuitPlan &P = cc->plan;
-    // forward
-    s = run_circuit(st, cc, gn, theta, stats);
-    if (s) return s;
-    // lambda = H psi (lambda buffer follows psi's layout)
-    HIPCHK(st, st->d_lam.ensure(st->bytes()), "alloc lambda");
-    svq_state_s lam_view;
-    lam_view.n = st->n;
-    lam_view.g = st->g;
-    lam_view.dtype = st->dtype;
-    lam_view.buf = st->d_lam.p;
-    lam_view.stream = st->stream;
-    lam_view.pos = st->pos;
-    lam_view.device = st->device;
-    s = sv_apply_hamiltonian(st, terms, n_terms, &lam_view);
-    lam_view.buf = nullptr;   // not owned
-    if (s) return s;
-    // E = Re <psi|lambda>
-    const int dg = dot_grid(st->N());
-    HIPCHK(st, st->d_extra.ensure(sizeof(double) * dg), "alloc extra");
-    HIPCHK(st, st->d_energy.ensure(sizeof(double)), "alloc energy");
-    double *edev = energy_dev ? energy_dev : (double *)st->d_energy.p;
-    HIPCHK(st, launch_dot_re(st->dbl(), st->buf, st->d_lam.p, st->N(), (double *)st->d_extra.p, st->stream), "dot");
-    HIPCHK(st, launch_sum((const double *)st->d_extra.p, dg, edev, st->stream), "sum");
-    // back to the circuit's final layout (both states)
+    // Every table and scratch buffer is prepared before the first launch, so
+    // that a failed allocation (ENOMEM) leaves the handle as it was.
+    // Pauli tables for the layout the forward pass ends in:
     {
-        std::vector<int> lp = st->pos;
-        s = relayout(st, st->d_lam.p, lp, P.pos_after);
-        if (s) return s;
-        s = relayout(st, st->buf, st->pos, P.pos_after);
+        const std::vector<int> keep = st->pos;
+        st->pos = P.pos_after;
+        CachedPaulis *cph = nullptr;
+        double msh = 0;
+        s = get_pauli_plan(st, terms, n_terms, SVQ_LAZY, &cph, &msh, true);
+        st->pos = keep;
         if (s) return s;
     }
-    // reverse sweep
+    // inverse ops with generators (chain-rule scale folded in)
     std::vector<OpDesc> inv = P.ops;
     fill_ops(gn, theta, P.op_gate, inv, true);
     for (size_t i = 0; i < inv.size(); ++i) {
@@ -860,31 +960,21 @@ svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *the
         inv[i].gslot = (g.param >= 0 && inv[i].gtype != GEN_NONE) ? P.op_gate[i] : -1;
         if (inv[i].gslot < 0) inv[i].gtype = GEN_NONE;
     }
-    HIPCHK(st, st->d_ops.ensure(sizeof(OpDesc) * std::max<size_t>(1, inv.size())), "alloc ops");
-    HIPCHK(st, hipMemcpyAsync(st->d_ops.p, inv.data(), sizeof(OpDesc) * inv.size(),
-                              hipMemcpyHostToDevice, st->stream),
-           "upload inverse ops");
-    const int nblocks = 1 << (st->n - P.k);
-    const int nwaves = (1 << (P.k - gate_rb(P.k))) / 64;
-    const int nper = nblocks * nwaves;
-    HIPCHK(st, st->d_gpart.ensure(sizeof(double) * (size_t)std::max(1, m) * nper), "alloc gpart");
-    for (auto it = P.steps.rbegin(); it != P.steps.rend(); ++it) {
-        if (it->type == 0) {
-            s = run_qr(st, st->buf, it->qr);
-            if (s) return s;
-            s = run_qr(st, st->d_lam.p, it->qr);
-            if (s) return s;
-        } else {
-            PassArgs a = P.passes[it->idx];
-            a.gslot_base = 0;
-            ProfScope ps(st, 4);
-            HIPCHK(st, launch_gate_pass(st->dbl(), P.k, true, st->buf, st->d_lam.p, a,
-                                        (const PhaseDesc *)cc->d_phases.p, (const OpDesc *)st->d_ops.p,
-                                        (double *)st->d_gpart.p, nblocks, st->stream),
-                   "adjoint_pass");
+    // Gates of the parametric ops of every pass, in the order the reverse pass
+    // visits them (phases and ops backwards): slot i of a pass's block
+    // partials belongs to gate ggates[goff[pass] + i].
+    std::vector<int> ggates, goff(P.passes.size() + 1, 0);
+    int gmax = 0;
+    for (size_t p = 0; p < P.passes.size(); ++p) {
+        const PassArgs &pa = P.passes[p];
+        for (int sidx = pa.nphase - 1; sidx >= 0; --sidx) {
+            const PhaseDesc &ph = P.phases[pa.phase0 + sidx];
+            for (int q = ph.nop - 1; q >= 0; --q)
+                if (inv[ph.op0 + q].gtype != GEN_NONE) ggates.push_back(P.op_gate[ph.op0 + q]);
         }
+        goff[p + 1] = (int)ggates.size();
+        gmax = std::max(gmax, goff[p + 1] - goff[p]);
     }
-    st->pos = pos0;
     // gradient reduction: CSR param -> gates
     std::vector<int> pptr(n_theta + 1, 0), pgate;
     for (int i = 0; i < m; ++i)
@@ -900,14 +990,82 @@ svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *the
                                      gn[i].kind == SVQ_CPHASE || gn[i].kind == SVQ_GIVENS))
                 pgate[fillp[gn[i].param]++] = i;
     }
+    const uint32_t nblocks = 1u << (st->n - P.k);
+    const int dg = dot_grid(st->N());
+    HIPCHK(st, st->d_lam.ensure(st->bytes()), "alloc lambda");
+    HIPCHK(st, st->d_extra.ensure(sizeof(double) * dg), "alloc extra");
+    HIPCHK(st, st->d_energy.ensure(sizeof(double)), "alloc energy");
+    HIPCHK(st, st->d_ops.ensure(sizeof(OpDesc) * std::max<size_t>(1, inv.size())), "alloc ops");
+    HIPCHK(st, st->d_gpart.ensure(sizeof(double) * (size_t)std::max(1, gmax) * nblocks), "alloc gpart");
+    HIPCHK(st, st->d_gop.ensure(sizeof(double) * (size_t)std::max(1, m)), "alloc gop");
+    HIPCHK(st, st->d_ggates.ensure(sizeof(int) * std::max<size_t>(1, ggates.size())), "alloc ggates");
     HIPCHK(st, st->d_pptr.ensure(sizeof(int) * pptr.size()), "alloc pptr");
     HIPCHK(st, st->d_pgate.ensure(sizeof(int) * std::max<size_t>(1, pgate.size())), "alloc pgate");
+    HIPCHK(st, st->d_grad.ensure(sizeof(double) * std::max(1, n_theta)), "alloc grad");
+    double *edev = energy_dev ? energy_dev : (double *)st->d_energy.p;
+    double *gdev = grad_dev ? grad_dev : (double *)st->d_grad.p;
+    // forward
+    s = run_circuit(st, cc, gn, theta, stats);
+    if (s) return s;
+    // lambda = H psi (lambda buffer follows psi's layout)
+    svq_state_s lam_view;
+    lam_view.n = st->n;
+    lam_view.g = st->g;
+    lam_view.dtype = st->dtype;
+    lam_view.buf = st->d_lam.p;
+    lam_view.stream = st->stream;
+    lam_view.pos = st->pos;
+    lam_view.device = st->device;
+    s = sv_apply_hamiltonian(st, terms, n_terms, &lam_view);
+    lam_view.buf = nullptr;   // not owned
+    if (s) return s;
+    // E = Re <psi|lambda>
+    HIPCHK(st, launch_dot_re(st->dbl(), st->buf, st->d_lam.p, st->N(), (double *)st->d_extra.p, st->stream), "dot");
+    HIPCHK(st, launch_sum((const double *)st->d_extra.p, dg, edev, st->stream), "sum");
+    // back to the circuit's final layout (both states)
+    {
+        std::vector<int> lp = st->pos;
+        s = relayout(st, st->d_lam.p, lp, P.pos_after);
+        if (s) return s;
+        s = relayout(st, st->buf, st->pos, P.pos_after);
+        if (s) return s;
+    }
+    // reverse sweep
+    HIPCHK(st, hipMemcpyAsync(st->d_ops.p, inv.data(), sizeof(OpDesc) * inv.size(),
+                              hipMemcpyHostToDevice, st->stream),
+           "upload inverse ops");
+    if (!ggates.empty())
+        HIPCHK(st, hipMemcpyAsync(st->d_ggates.p, ggates.data(), sizeof(int) * ggates.size(),
+                                  hipMemcpyHostToDevice, st->stream),
+               "upload ggates");
+    for (auto it = P.steps.rbegin(); it != P.steps.rend(); ++it) {
+        if (it->type == 0) {
+            s = run_qr(st, st->buf, it->qr);
+            if (s) return s;
+            s = run_qr(st, st->d_lam.p, it->qr);
+            if (s) return s;
+        } else {
+            const PassArgs &a = P.passes[it->idx];
+            {
+                ProfScope ps(st, 4);
+                HIPCHK(st, launch_gate_pass(st->dbl(), P.k, true, st->buf, st->d_lam.p, a,
+                                            (const PhaseDesc *)cc->d_phases.p,
+                                            (const OpDesc *)st->d_ops.p, (double *)st->d_gpart.p,
+                                            (int)nblocks, st->stream),
+                       "adjoint_pass");
+            }
+            const int g0 = goff[it->idx], gn_pass = goff[it->idx + 1] - g0;
+            HIPCHK(st, launch_grad_tiles((const double *)st->d_gpart.p, nblocks, gn_pass,
+                                         (const int *)st->d_ggates.p + g0, (double *)st->d_gop.p,
+                                         st->stream),
+                   "grad_tiles");
+        }
+    }
+    st->pos = pos0;
     HIPCHK(st, hipMemcpyAsync(st->d_pptr.p, pptr.data(), sizeof(int) * pptr.size(), hipMemcpyHostToDevice, st->stream), "upload pptr");
     if (!pgate.empty())
         HIPCHK(st, hipMemcpyAsync(st->d_pgate.p, pgate.data(), sizeof(int) * pgate.size(), hipMemcpyHostToDevice, st->stream), "upload pgate");
-    HIPCHK(st, st->d_grad.ensure(sizeof(double) * std::max(1, n_theta)), "alloc grad");
-    double *gdev = grad_dev ? grad_dev : (double *)st->d_grad.p;
-    HIPCHK(st, launch_grad_reduce((const double *)st->d_gpart.p, nper, (const int *)st->d_pptr.p,
+    HIPCHK(st, launch_grad_reduce((const double *)st->d_gop.p, 1, (const int *)st->d_pptr.p,
                                   (const int *)st->d_pgate.p, n_theta, gdev, st->stream),
            "grad_reduce");
     if (stats) {
@@ -919,7 +1077,7 @@ svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *the
         HIPCHK(st, hipMemcpyAsync(energy_host, edev, sizeof(double), hipMemcpyDeviceToHost, st->stream), "D2H");
     if (grad_host && n_theta)
         HIPCHK(st, hipMemcpyAsync(grad_host, gdev, sizeof(double) * n_theta, hipMemcpyDeviceToHost, st->stream), "D2H");
-    // pptr/pgate host vectors must outlive the async copies
+    // pptr/pgate/ggates host vectors must outlive the async copies
     HIPCHK(st, hipStreamSynchronize(st->stream), "sync");
     return SVQ_OK;
 }
@@ -1056,6 +1214,7 @@ struct svq_batch_s {
 namespace {
 
 svq_status batch_hip_fail(svq_batch b, hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory) return fail(SVQ_ENOMEM, std::string(what) + ": out of device memory");
     if (b) b->poisoned = true;
     return fail(SVQ_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -1461,7 +1620,9 @@ svq_status sv_expectation_qsu(svq_state st, const svq_pauli *terms, int n_terms,
     if (n_terms == 0) {
         HIPCHK(st, hipMemsetAsync(edev, 0, sizeof(double), st->stream), "zero energy");
     } else {
+        const int dg = dot_grid(st->N());
         HIPCHK(st, st->d_lam.ensure(st->bytes()), "alloc psi'");
+        HIPCHK(st, st->d_extra.ensure(sizeof(double) * dg), "alloc extra");
         DevBuf d_wt;
         HIPCHK(st, d_wt.ensure(sizeof(WideTerm) * n_terms), "alloc terms");
         HIPCHK(st, hipMemcpyAsync(d_wt.p, wt.data(), sizeof(WideTerm) * n_terms,
@@ -1489,8 +1650,6 @@ svq_status sv_expectation_qsu(svq_state st, const svq_pauli *terms, int n_terms,
                 first = false;
             }
         }
-        const int dg = dot_grid(st->N());
-        HIPCHK(st, st->d_extra.ensure(sizeof(double) * dg), "alloc extra");
         HIPCHK(st, launch_dot_re(st->dbl(), st->buf, st->d_lam.p, st->N(), (double *)st->d_extra.p,
                                  st->stream),
                "dot");

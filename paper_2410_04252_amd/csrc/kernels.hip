@@ -301,24 +301,28 @@ __device__ __forceinline__ void apply_op(Regs<R, NR> &v, const OpDesc &o) {
 }
 
 // ---- adjoint: 2 Im <lambda|K|psi> over this thread's amplitudes ------------
+// Products are formed in the state's precision and summed in FP64.  The
+// generator entries of DIAG1/MIX1 carry the angle's scale (chain rule); the
+// hard-coded CPHASE and GIVENS generators take it from k[0].
 
 template <int B0, int B1, typename R, int NR>
 __device__ __forceinline__ double gen_value(const Regs<R, NR> &x, const Regs<R, NR> &l,
                                             const OpDesc &o) {
-    R acc = 0;
+    double acc = 0.0;
     if (o.gtype == GEN_DIAG1) {
         const R k0 = (R)o.k[0], k1 = (R)o.k[1];
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             const R kk = ((j >> B0) & 1) ? k1 : k0;
-            acc += kk * (l.re[j] * x.im[j] - l.im[j] * x.re[j]);   // Im(conj(l) x)
+            acc += (double)(kk * (l.re[j] * x.im[j] - l.im[j] * x.re[j]));   // Im(conj(l) x)
         }
     } else if (o.gtype == GEN_CPHASE) {
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (!((j >> B0) & 1) || !((j >> B1) & 1)) continue;
-            acc -= l.re[j] * x.im[j] - l.im[j] * x.re[j];
+            acc -= (double)(l.re[j] * x.im[j] - l.im[j] * x.re[j]);
         }
+        acc *= o.k[0];
     } else if (o.gtype == GEN_MIX1) {
         const R k00r = (R)o.k[0], k00i = (R)o.k[1], k01r = (R)o.k[2], k01i = (R)o.k[3];
         const R k10r = (R)o.k[4], k10i = (R)o.k[5], k11r = (R)o.k[6], k11i = (R)o.k[7];
@@ -330,18 +334,19 @@ __device__ __forceinline__ double gen_value(const Regs<R, NR> &x, const Regs<R, 
             const R y0i = k00r * x.im[j] + k00i * x.re[j] + k01r * x.im[j1] + k01i * x.re[j1];
             const R y1r = k10r * x.re[j] - k10i * x.im[j] + k11r * x.re[j1] - k11i * x.im[j1];
             const R y1i = k10r * x.im[j] + k10i * x.re[j] + k11r * x.im[j1] + k11i * x.re[j1];
-            acc += l.re[j] * y0i - l.im[j] * y0r + l.re[j1] * y1i - l.im[j1] * y1r;
+            acc += (double)(l.re[j] * y0i - l.im[j] * y0r) + (double)(l.re[j1] * y1i - l.im[j1] * y1r);
         }
     } else {   // GEN_GIVENS: Im<l|K|x> = (Re(conj(l_w) x_u) - Re(conj(l_u) x_w)) / 2
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (j & ((1 << B0) | (1 << B1))) continue;
             const int ju = j | (1 << B0), jw = j | (1 << B1);
-            acc += (R)0.5 * (l.re[jw] * x.re[ju] + l.im[jw] * x.im[ju]
-                             - l.re[ju] * x.re[jw] - l.im[ju] * x.im[jw]);
+            acc += (double)(l.re[jw] * x.re[ju] + l.im[jw] * x.im[ju])
+                 - (double)(l.re[ju] * x.re[jw] + l.im[ju] * x.im[jw]);
         }
+        acc *= 0.5 * o.k[0];
     }
-    return 2.0 * (double)acc;
+    return 2.0 * acc;
 }
 
 #define SVQ_G1(I)                                                          \
@@ -464,11 +469,17 @@ __device__ __forceinline__ void store_regs(const Regs<R, NR> &v, V *__restrict__
     }
 }
 
+// Gradient values of one adjoint pass are collected per wave in LDS and
+// summed over the block's waves in a fixed order, GCAP ops at a time.
+constexpr int kGradCap = 32;
+
 // One gate pass (forward), or one reverse adjoint pass when ADJ: psi and
 // lam both get U^dagger of every op in reverse order, and each parametric op
-// first records 2 Im <lam|K|psi> per wave into gpart.  One block per tile:
-// load with the first phase's mapping, run the phases (an LDS transpose
-// between consecutive ones), store with the last phase's mapping.
+// first records 2 Im <lam|K|psi>.  Its i-th parametric op (in the order the
+// pass visits them) writes the block's FP64 sum to gpart[i * ntiles + tile].
+// One block per tile: load with the first phase's mapping, run the phases (an
+// LDS transpose between consecutive ones), store with the last phase's
+// mapping.
 template <typename R, int K, int RB, bool ADJ, bool OFF32>
 __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
     typename V2T<R>::type *__restrict__ psi, typename V2T<R>::type *__restrict__ lam,
@@ -480,6 +491,7 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
     constexpr int NW = NT / 64;
     constexpr int NWB = K - RB - 6;
     __shared__ V lds[(ADJ ? 2 : 1) << K];
+    __shared__ double gacc[ADJ ? kGradCap * NW : 1];
     if (blockIdx.x >= ntiles) return;
     // Workgroups are dealt to the 8 XCDs round robin (block b runs on XCD
     // b mod 8); give each XCD one contiguous eighth of the tiles.  Every tile
@@ -501,6 +513,20 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
         load_regs<V, R, NR, RB, K, OFF32>(v, psi + base, tp0, mc);
         if constexpr (ADJ) load_regs<V, R, NR, RB, K, OFF32>(w, lam + base, tp0, mc);
     }
+    // adjoint: ng values pending in gacc, nflushed already written
+    int ng = 0, nflushed = 0;
+    auto flush = [&]() {
+        __syncthreads();
+        if ((int)threadIdx.x < ng) {
+            double sum = 0.0;
+#pragma unroll
+            for (int wv = 0; wv < NW; ++wv) sum += gacc[threadIdx.x * NW + wv];
+            gpart[(size_t)(nflushed + threadIdx.x) * ntiles + tile] = sum;
+        }
+        nflushed += ng;
+        ng = 0;
+        __syncthreads();
+    };
     for (int s = 0; s < np; ++s) {
         const PhaseDesc &Pc = phases[a.phase0 + (ADJ ? np - 1 - s : s)];
         if (s > 0) {
@@ -544,7 +570,8 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
             if constexpr (ADJ) {
                 if (o.gtype != GEN_NONE) {
                     const double gv = wave_sum(op_gradient<R, NR, RB>(v, w, o));
-                    if (lane == 0) gpart[((size_t)o.gslot * ntiles + tile) * NW + wave] = gv;
+                    if (lane == 0) gacc[ng * NW + wave] = gv;
+                    if (++ng == kGradCap) flush();
                 }
                 apply_op<R, NR, RB>(w, o);
             }
@@ -557,7 +584,10 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
     RegMap<RB, K> mL;
     mL.init(PL, a.tphys);
     store_regs<V, R, NR, RB, K, OFF32>(v, psi + base, tpL, mL);
-    if constexpr (ADJ) store_regs<V, R, NR, RB, K, OFF32>(w, lam + base, tpL, mL);
+    if constexpr (ADJ) {
+        store_regs<V, R, NR, RB, K, OFF32>(w, lam + base, tpL, mL);
+        if (ng) flush();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1112,6 +1142,19 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double *__restrict__ 
     if (threadIdx.x == 0) grad[p] = s;
 }
 
+// Sum of one adjoint pass's block partials over the tiles (fixed order):
+// gop[gates[i]] = sum_t gpart[i * ntiles + t].
+__global__ __launch_bounds__(256) void k_grad_tiles(const double *__restrict__ gpart,
+                                                     uint32_t ntiles, const int *__restrict__ gates,
+                                                     double *__restrict__ gop) {
+    __shared__ double red[4];
+    const double *src = gpart + (size_t)blockIdx.x * ntiles;
+    double acc = 0.0;
+    for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) acc += src[t];
+    const double sum = block_sum(acc, red);
+    if (threadIdx.x == 0) gop[gates[blockIdx.x]] = sum;
+}
+
 template <typename V>
 __global__ __launch_bounds__(256) void k_fill_basis(V *__restrict__ psi, uint64_t N, uint64_t idx) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < N;
@@ -1344,6 +1387,13 @@ hipError_t launch_grad_reduce(const double *gpart, int nper, const int *pptr, co
                               int nparam, double *grad, hipStream_t s) {
     if (nparam == 0) return hipSuccess;
     hipLaunchKernelGGL(k_grad_reduce, dim3(nparam), dim3(256), 0, s, gpart, nper, pptr, pgate, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_tiles(const double *gpart, uint32_t ntiles, int nslots, const int *gates,
+                             double *gop, hipStream_t s) {
+    if (nslots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_tiles, dim3(nslots), dim3(256), 0, s, gpart, ntiles, gates, gop);
     return hipGetLastError();
 }
 

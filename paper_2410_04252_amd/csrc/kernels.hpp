@@ -56,6 +56,10 @@ hipError_t launch_dot_re(bool dbl, const void *a, const void *b, uint64_t N, dou
                          hipStream_t s);
 hipError_t launch_grad_reduce(const double *gpart, int nper, const int *pptr, const int *pgate,
                               int nparam, double *grad, hipStream_t s);
+// gop[gates[i]] = sum over tiles of gpart[i * ntiles + t], i < nslots (the
+// block partials of one adjoint pass).
+hipError_t launch_grad_tiles(const double *gpart, uint32_t ntiles, int nslots, const int *gates,
+                             double *gop, hipStream_t s);
 hipError_t launch_fill_basis(bool dbl, void *psi, uint64_t N, uint64_t idx, hipStream_t s);
 // Reset counters (fill kernel) and launch the persistent batch kernel.
 hipError_t launch_batch(const BatchArgs &a, int32_t *counters, int ncounters, hipStream_t s,

@@ -48,8 +48,10 @@ std::string normalize_gates(int n, const svq_gate *gates, int m, int n_theta,
         bool parametric = s.kind == SVQ_RX || s.kind == SVQ_RY || s.kind == SVQ_RZ ||
                           s.kind == SVQ_CPHASE || s.kind == SVQ_GIVENS;
         if (!parametric && s.param >= 0) return "gate " + std::to_string(i) + ": kind takes no parameter";
-        g.angle = s.angle;
-        if (s.param < 0 && !std::isfinite(s.angle)) return "gate " + std::to_string(i) + ": non-finite angle";
+        g.offset = s.offset;
+        g.scale = s.param >= 0 ? s.scale : 0.0;
+        if (!std::isfinite(s.offset) || (s.param >= 0 && !std::isfinite(s.scale)))
+            return "gate " + std::to_string(i) + ": non-finite angle offset or scale";
         if (s.kind == SVQ_U1 || s.kind == SVQ_U2) {
             int cnt = s.kind == SVQ_U1 ? 8 : 32;
             for (int j = 0; j < cnt; ++j) {
@@ -866,7 +868,7 @@ void fill_ops(const std::vector<GateN> &gates, const double *theta, const std::v
     for (size_t i = 0; i < ops.size(); ++i) {
         const GateN &g = gates[op_gate[i]];
         OpDesc &o = ops[i];
-        const double t = g.param >= 0 ? theta[g.param] : g.angle;
+        const double t = g.param >= 0 ? g.scale * theta[g.param] + g.offset : g.offset;
         const double c = std::cos(0.5 * t), s = std::sin(0.5 * t);
         double *m = o.m;
         std::memset(m, 0, sizeof(o.m));
@@ -913,6 +915,15 @@ void fill_ops(const std::vector<GateN> &gates, const double *theta, const std::v
             break;
         }
         if (g.param < 0) o.gtype = GEN_NONE;
+        // Chain rule: the angle is scale * theta + offset, so the derivative
+        // by theta is scale * 2 Im <lambda|K|psi>; the scale is folded into
+        // the explicit generator entries, or kept in k[0] for the kinds whose
+        // generator the kernels hard-code.
+        if (o.gtype == GEN_MIX1 || o.gtype == GEN_DIAG1) {
+            for (double &kv : o.k) kv *= g.scale;
+        } else if (o.gtype == GEN_CPHASE || o.gtype == GEN_GIVENS) {
+            o.k[0] = g.scale;
+        }
         if (!inverse) {
             set_shears(o);
             continue;

@@ -24,7 +24,8 @@ struct GateN {
     int nq = 1;
     int q[2] = {0, 0};
     int param = -1;
-    double angle = 0.0;
+    double scale = 1.0;    // angle = scale * theta[param] + offset (param >= 0)
+    double offset = 0.0;   // the whole angle when param < 0
     double mat[32] = {0};
     uint64_t tmask = 0;    // all qubits of the gate
     uint64_t mixmask = 0;  // qubits whose bit value the gate mixes

@@ -48,13 +48,14 @@ enum OpType : int32_t {
     OP_ROTY = 7,    // real 2x2 [[c, -s], [s, c]] on b0;         m = {c, s}
 };
 
-// Generator K of a parametric op (U = exp(-i t K)), for the adjoint sweep.
+// Generator K of a parametric op (U = exp(-i t K)), for the adjoint sweep,
+// times the gate's angle scale d t / d theta (chain rule).
 enum GenType : int32_t {
     GEN_NONE = 0,
     GEN_DIAG1 = 1,   // diag(k0, k1) on b0 (real)
     GEN_MIX1 = 2,    // 2x2 Hermitian on b0: k = row-major complex 2x2
-    GEN_GIVENS = 3,  // (X_b0 Y_b1 - Y_b0 X_b1)/4
-    GEN_CPHASE = 4,  // -|11><11| on (b0, b1)
+    GEN_GIVENS = 3,  // k0 (X_b0 Y_b1 - Y_b0 X_b1)/4
+    GEN_CPHASE = 4,  // -k0 |11><11| on (b0, b1)
 };
 
 // Unit-modulus ops (ROTY, GIVENS: a real rotation of an amplitude pair;
@@ -88,7 +89,7 @@ struct PhaseDesc {
 struct PassArgs {
     int32_t nphase;
     int32_t phase0;
-    int32_t gslot_base;   // adjoint partial-buffer offset of this pass
+    int32_t spare;
     int32_t nblocks;
     int8_t tphys[16];     // physical bit of tile-local bit j (ascending)
 };

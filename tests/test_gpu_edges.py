@@ -10,6 +10,12 @@ from tolerances import AMP, energy_ok
 pytestmark = pytest.mark.gpu
 
 
+def _cdt(dtype):
+    """numpy dtype of a handle: inputs are drawn in it, so the oracle and the
+    GPU start from the same amplitudes."""
+    return np.complex64 if dtype == "c64" else np.complex128
+
+
 @pytest.fixture(scope="module")
 def P():
     import torch
@@ -37,7 +43,7 @@ def test_empty_circuit_and_empty_hamiltonian(P, dtype, sched):
     No terms: the energy is exactly 0."""
     n, g = 12, 2
     _print(f"empty inputs {dtype} sched={sched}")
-    v = W.random_state(n, 901)
+    v = W.random_state(n, 901, _cdt(dtype))
     st = P.State(n, g, dtype)
     st.set_amplitudes(v)
     stats = st.apply_gates([], theta=[], sched=sched)
@@ -56,7 +62,7 @@ def test_smallest_states(P, dtype, n, g):
     tile per chunk, for gate passes and Pauli passes (one or two cube bits)."""
     _print(f"smallest n={n} g={g} {dtype}")
     circ = W.random_circuit(n, 60, 910 + n)
-    v = W.random_state(n, 911 + n)
+    v = W.random_state(n, 911 + n, _cdt(dtype))
     ref = oracle.apply_circuit(v, circ.gates, circ.theta)
     ham = W.random_pauli(n, 37, 912 + n)
     for sched in (P.LAZY, P.EAGER):
@@ -90,7 +96,7 @@ def test_ragged_term_counts_in_one_group(P, dtype, nterms):
         zs.add(z)
         strings.append((x, z, float(rng.normal(0.0, 0.3))))
     ham = _ham(n, strings)
-    v = W.random_state(n, 921)
+    v = W.random_state(n, 921, _cdt(dtype))
     e_ref = oracle.expectation(v, ham)
     for sched in (P.LAZY, P.EAGER):
         st = P.State(n, g, dtype)
@@ -115,7 +121,7 @@ def test_identity_and_global_only_terms(P, dtype):
                (1 << top[2], (1 << top[2]) | 1, 0.3),
                (0, (1 << top[0]) | (1 << top[1]) | (1 << top[2]), 0.5)]
     ham = _ham(n, strings)
-    v = W.random_state(n, 930)
+    v = W.random_state(n, 930, _cdt(dtype))
     e_ref = oracle.expectation(v, ham)
     for sched in (P.LAZY, P.EAGER):
         st = P.State(n, g, dtype)
@@ -144,7 +150,7 @@ def test_single_gate_on_global_qubits(P, dtype, kind):
         circ = W.Circuit(n, [(kind, qs, 0)], np.array([0.917]), 0)
     else:
         circ = W.Circuit(n, [(kind, qs, -1)], np.zeros(0), 0)
-    v = W.random_state(n, 940)
+    v = W.random_state(n, 940, _cdt(dtype))
     ref = oracle.apply_circuit(v, circ.gates, circ.theta)
     for sched in (P.LAZY, P.EAGER):
         st = P.State(n, g, dtype)

@@ -6,9 +6,15 @@ import pytest
 
 import oracle
 import workloads as W
-from tolerances import AMP, energy_ok
+from tolerances import AMP, amp_ok, energy_ok, grad_ok
 
 pytestmark = pytest.mark.gpu
+
+
+def _cdt(dtype):
+    """numpy dtype of a handle: inputs are drawn in it, so the oracle and the
+    GPU start from the same amplitudes."""
+    return np.complex64 if dtype == "c64" else np.complex128
 
 
 @pytest.fixture(scope="module")
@@ -63,24 +69,26 @@ CIRCS = {
     "fabric16": lambda: (W.fabric(16, 8, 11), 3),
     "random14": lambda: (W.random_circuit(14, 120, 12), 3),
 }
+# local qubits n - g of each circuit: a tile is at most that wide
+_LOCAL = {"hea12": 10, "fabric16": 13, "random14": 11}
 
 
 @pytest.mark.parametrize("sched", [0, 1])
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("name", list(CIRCS))
-@pytest.mark.parametrize("k", [8, 10, 12])
+@pytest.mark.parametrize("name,k", [(nm, k) for k in (8, 10, 12) for nm in CIRCS
+                                    if k <= _LOCAL[nm]])
 def test_circuit_parity(P, name, dtype, sched, k):
     circ, g = CIRCS[name]()
     n = circ.n
-    if k > n - g:
-        pytest.skip("tile wider than the local qubits")
+    assert k <= n - g
     _print(f"circuit {name} {dtype} sched={sched} k={k}")
     ref = oracle.run_circuit(circ)
     st = P.State(n, g, dtype)
     st.set_basis(circ.psi0_index)
     stats = st.apply(circ, sched=sched, tile_k=k)
     got = st.get_amplitudes()
-    assert np.max(np.abs(got - ref)) < AMP[dtype]
+    ok, mx, rl2 = amp_ok(got, ref, dtype)
+    assert ok, (mx, rl2)
     assert stats.n_gate_passes >= 1
     st.close()
 
@@ -89,13 +97,14 @@ def test_circuit_parity(P, name, dtype, sched, k):
 def test_circuit_random_state_input(P, dtype):
     n, g = 15, 3
     circ = W.fabric(n, 6, 21)
-    v = W.random_state(n, 22)
+    v = W.random_state(n, 22, _cdt(dtype))
     ref = oracle.apply_circuit(v, circ.gates, circ.theta)
     st = P.State(n, g, dtype)
     st.set_amplitudes(v)
     st.apply(circ)
     got = st.get_amplitudes()
-    assert np.max(np.abs(got - ref)) < (1e-5 if dtype == "c64" else 1e-12)
+    ok, mx, rl2 = amp_ok(got, ref, dtype)
+    assert ok, (mx, rl2)
     st.close()
 
 
@@ -112,7 +121,7 @@ HAMS = {
 def test_expectation_parity(P, name, dtype, sched):
     n, g, ham = HAMS[name]()
     _print(f"expectation {name} {dtype} sched={sched}")
-    v = W.random_state(n, 40 + n)
+    v = W.random_state(n, 40 + n, _cdt(dtype))
     e_ref = oracle.expectation(v, ham)
     st = P.State(n, g, dtype)
     st.set_amplitudes(v)
@@ -131,14 +140,15 @@ def test_grad_parity_small(P):
     ham = W.jw_terms(n, 80, 52)
     e_ref, g_ref = oracle.adjoint_grad(circ, ham)
     psi_ref = oracle.run_circuit(circ)
-    for dtype, rel in (("c64", 1e-5), ("c128", 1e-11)):
+    for dtype in ("c64", "c128"):
         _print(f"grad {dtype}")
         st = P.State(n, g, dtype)
         st.set_basis(circ.psi0_index)
         e, grad, _ = st.grad(circ, ham)
         ok, erel = energy_ok(e, e_ref, psi_ref, ham, dtype)
         assert ok, erel
-        assert np.linalg.norm(grad - g_ref) <= rel * np.linalg.norm(g_ref)
+        ok, grel = grad_ok(grad, g_ref, ham, dtype)
+        assert ok, (dtype, grel)
         st.close()
 
 
@@ -188,7 +198,7 @@ def test_unit_modulus_ops_at_boundary_angles(P, dtype):
         for kd in ("Z", "S", "T"):
             gates.append((kd, ((q + 3) % n,), -1))
     circ = W.Circuit(n, gates, np.array(theta), 0)
-    v = W.random_state(n, 77)
+    v = W.random_state(n, 77, _cdt(dtype))
     ref = oracle.apply_circuit(v, circ.gates, circ.theta)
     _print(f"boundary angles {dtype}")
     for sched in (P.LAZY, P.EAGER):
@@ -207,8 +217,8 @@ def test_unit_modulus_ops_at_boundary_angles(P, dtype):
     st.close()
     ok, erel = energy_ok(e, e_ref, None, ham, dtype)
     assert ok, erel
-    tol = 1e-5 if dtype == "c64" else 1e-11
-    assert np.linalg.norm(grad - g_ref) <= tol * max(1e-3, np.linalg.norm(g_ref))
+    ok, grel = grad_ok(grad, g_ref, ham, dtype)
+    assert ok, grel
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
@@ -306,8 +316,8 @@ def test_dense_matrix_gates_forward_and_gradient(P, dtype):
     st.close()
     ok, rel = energy_ok(e, oracle.expectation(ref, ham), ref, ham, dtype)
     assert ok, rel
-    tol = 1e-5 if dtype == "c64" else 1e-10
-    assert np.linalg.norm(grad - g_ref) <= tol * max(1e-3, np.linalg.norm(g_ref))
+    ok, grel = grad_ok(grad, g_ref, ham, dtype)
+    assert ok, grel
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])

@@ -292,7 +292,7 @@ def config(name: str) -> dict:
     if name == "grad24":
         c = fabric(24, 1000, SEED_BASE + 4, max_params=400)
         h = jw_terms(24, 1000, SEED_BASE + 4 + 1000)
-        return dict(name=name, circuit=c, ham=h, g=0, k=0, dtype="c64")
+        return dict(name=name, circuit=c, ham=h, g=5, k=0, dtype="c64")
     raise KeyError(name)
 
 
