@@ -156,6 +156,21 @@ svq_status sv_device_ptr(svq_state st, void **ptr_out);
 svq_status sv_apply_circuit(svq_state st, const svq_gate *gates, int m, const double *theta,
                             int n_theta, svq_sched sched, int tile_k, svq_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * sv_apply_circuit, but the phase and op descriptor tables of the call live in
+ * a static 4 MiB device array of the library (one per GPU, kept until the
+ * process ends) instead of buffers the handle allocates, so the call makes no
+ * device allocation.  The handle should borrow its state buffer (sv_create
+ * with dev_buf).  Host-side plans are cached on the handle as usual.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU (two
+ * streams or threads) race and must be serialised by the caller.  Errors: as
+ * sv_apply_circuit, plus ESHAPE when the tables exceed 4 MiB (about 11,000
+ * gates at 352 bytes each; nothing runs then). */
+svq_status sv_apply_circuit_static(svq_state st, const svq_gate *gates, int m,
+                                   const double *theta, int n_theta, svq_sched sched,
+                                   int tile_k, svq_stats *stats);
+
 /* Reorder to a new layout: new_pos[q] = physical bit of logical qubit q (a
  * permutation of 0..n-1).  An involutive relayout (a set of disjoint bit
  * transpositions, as every QR of Section "Qubit reordering" is) runs as one

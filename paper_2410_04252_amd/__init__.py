@@ -50,7 +50,8 @@ class SvqError(RuntimeError):
 
 
 EXPORTS = ("sv_create", "sv_destroy", "sv_set_basis", "sv_set_amplitudes", "sv_get_amplitudes",
-           "sv_get_layout", "sv_plan_dump", "sv_device_ptr", "sv_apply_circuit", "sv_qr_permute",
+           "sv_get_layout", "sv_plan_dump", "sv_device_ptr", "sv_apply_circuit",
+           "sv_apply_circuit_static", "sv_qr_permute",
            "sv_expectation", "sv_expectation_qsu", "sv_apply_hamiltonian", "sv_grad", "sv_plan_circuit",
            "sv_plan_paulis", "sv_plan_ops", "sv_tune_circuit", "sv_tune_paulis",
            "sv_batch_tune", "sv_tune_save", "sv_tune_load", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
@@ -73,6 +74,7 @@ def _load():
     L.sv_plan_dump.argtypes = [vp, ctypes.c_char_p, c_size_t, POINTER(c_size_t)]
     L.sv_apply_circuit.argtypes = [vp, POINTER(svq_gate), c_int, POINTER(c_double), c_int, c_int,
                                    c_int, POINTER(svq_stats)]
+    L.sv_apply_circuit_static.argtypes = L.sv_apply_circuit.argtypes
     L.sv_qr_permute.argtypes = [vp, POINTER(c_int32)]
     L.sv_expectation.argtypes = [vp, POINTER(svq_pauli), c_int, c_int, POINTER(c_double),
                                  POINTER(c_double), POINTER(c_double), POINTER(svq_stats)]
@@ -228,6 +230,16 @@ def sv_apply_circuit(h, gates_c, m, theta, n_theta, sched, tile_k=0):
     st = svq_stats()
     th = np.ascontiguousarray(theta, dtype=np.float64) if n_theta else np.zeros(1)
     _check(lib.sv_apply_circuit(h, gates_c, m, _dptr(th), n_theta, sched, tile_k, byref(st)))
+    return st
+
+
+def sv_apply_circuit_static(h, gates_c, m, theta, n_theta, sched, tile_k=0):
+    """sv_apply_circuit without device allocation (tables in the library's
+    static scratch)."""
+    st = svq_stats()
+    th = np.ascontiguousarray(theta, dtype=np.float64) if n_theta else np.zeros(1)
+    _check(lib.sv_apply_circuit_static(h, gates_c, m, _dptr(th), n_theta, sched, tile_k,
+                                       byref(st)))
     return st
 
 

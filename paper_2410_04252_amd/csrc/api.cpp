@@ -64,6 +64,13 @@ struct CachedCircuit {
     std::shared_ptr<const std::string> json;   // sv_plan_dump text
 };
 
+// Host-only circuit plan (sv_apply_circuit_static keeps its tables in the
+// library's static device scratch, not in per-plan device buffers).
+struct HostCircuit {
+    CircuitPlan plan;
+    std::shared_ptr<const std::string> json;
+};
+
 struct CachedPaulis {
     PauliPlan plan;
     std::vector<WideTerm> wide;
@@ -176,6 +183,7 @@ struct svq_state_s {
     bool poisoned = false;
     std::map<std::string, std::unique_ptr<CachedCircuit>> ccache;
     std::map<std::string, std::unique_ptr<CachedPaulis>> pcache;
+    std::map<std::string, std::unique_ptr<HostCircuit>> hcache;
     std::shared_ptr<const std::string> last_plan;   // JSON of the last executed plan
     DevBuf d_ops, d_partials, d_chunks, d_extra, d_lam, d_gpart, d_gop, d_ggates, d_pptr, d_pgate,
         d_energy, d_grad;
@@ -516,16 +524,10 @@ svq_status check_theta(const std::vector<GateN> &gates, const double *theta, int
 }
 
 // Forward circuit application with an existing plan.
-svq_status run_circuit(svq_state st, CachedCircuit *cc, const std::vector<GateN> &gates,
-                       const double *theta, svq_stats *stats) {
-    CircuitPlan &P = cc->plan;
-    st->last_plan = cc->json;
-    std::vector<OpDesc> ops = P.ops;
-    fill_ops(gates, theta, P.op_gate, ops, false);
-    HIPCHK(st, st->d_ops.ensure(sizeof(OpDesc) * std::max<size_t>(1, ops.size())), "alloc ops");
-    HIPCHK(st, hipMemcpyAsync(st->d_ops.p, ops.data(), sizeof(OpDesc) * ops.size(),
-                              hipMemcpyHostToDevice, st->stream),
-           "upload ops");
+// The QR and gate-pass launches of a circuit plan whose phase and op tables
+// are already on the device.
+svq_status run_circuit_steps(svq_state st, const CircuitPlan &P, const PhaseDesc *phases_dev,
+                             const OpDesc *ops_dev, svq_stats *stats) {
     double bytes = 0.0;
     for (const Step &s : P.steps) {
         if (s.type == 0) {
@@ -535,10 +537,8 @@ svq_status run_circuit(svq_state st, CachedCircuit *cc, const std::vector<GateN>
         } else {
             const PassArgs &a = P.passes[s.idx];
             ProfScope ps(st, 0);
-            HIPCHK(st, launch_gate_pass(st->dbl(), P.k, false, st->buf, nullptr, a,
-                                        (const PhaseDesc *)cc->d_phases.p,
-                                        (const OpDesc *)st->d_ops.p, nullptr, a.nblocks,
-                                        st->stream),
+            HIPCHK(st, launch_gate_pass(st->dbl(), P.k, false, st->buf, nullptr, a, phases_dev,
+                                        ops_dev, nullptr, a.nblocks, st->stream),
                    "gate_pass");
             bytes += 2.0 * (double)st->bytes();
         }
@@ -552,6 +552,20 @@ svq_status run_circuit(svq_state st, CachedCircuit *cc, const std::vector<GateN>
         stats->bytes += bytes;
     }
     return SVQ_OK;
+}
+
+svq_status run_circuit(svq_state st, CachedCircuit *cc, const std::vector<GateN> &gates,
+                       const double *theta, svq_stats *stats) {
+    CircuitPlan &P = cc->plan;
+    st->last_plan = cc->json;
+    std::vector<OpDesc> ops = P.ops;
+    fill_ops(gates, theta, P.op_gate, ops, false);
+    HIPCHK(st, st->d_ops.ensure(sizeof(OpDesc) * std::max<size_t>(1, ops.size())), "alloc ops");
+    HIPCHK(st, hipMemcpyAsync(st->d_ops.p, ops.data(), sizeof(OpDesc) * ops.size(),
+                              hipMemcpyHostToDevice, st->stream),
+           "upload ops");
+    return run_circuit_steps(st, P, (const PhaseDesc *)cc->d_phases.p, (const OpDesc *)st->d_ops.p,
+                             stats);
 }
 
 std::string pauli_key(const svq_pauli *terms, int nt, const svq_state_s *st, svq_sched sched,
@@ -674,6 +688,39 @@ svq_status run_expectation(svq_state st, CachedPaulis *cp, double *energy_dev, d
         stats->n_groups += (int)P.group_x.size();
         stats->bytes += bytes;
     }
+    return SVQ_OK;
+}
+
+}  // namespace
+
+// ---- static device scratch of sv_apply_circuit_static ------------------------
+// At most 4 MiB per GPU, held until the process ends.
+constexpr size_t kStaticScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+// One array per GPU in the library's code object: the phase and op descriptor
+// tables of the call.  Host code never passes `scratch` itself to a kernel
+// or a copy (on the host the name is only a stand-in); it resolves the array's
+// device address once per device with hipGetSymbolAddress and uses that.
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices];
+
+// The device address of this GPU's scratch (the handle's device is current).
+svq_status static_scratch(svq_state st, void **out) {
+    if (st->device < 0 || st->device >= kMaxDevices) return fail(SVQ_EUNSUP, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (!g_scratch_ptr[st->device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SVQ_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[st->device] = p;
+    }
+    *out = g_scratch_ptr[st->device];
     return SVQ_OK;
 }
 
@@ -831,6 +878,65 @@ svq_status sv_apply_circuit(svq_state st, const svq_gate *gates, int m, const do
     if (s) return s;
     if (stats) stats->ms_plan = ms;
     return run_circuit(st, cc, gn, theta, stats);
+}
+
+svq_status sv_apply_circuit_static(svq_state st, const svq_gate *gates, int m, const double *theta,
+                                   int n_theta, svq_sched sched, int tile_k, svq_stats *stats) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    if (m < 0 || (m > 0 && !gates) || n_theta < 0) return fail(SVQ_EINVAL, "bad gate list");
+    if (sched != SVQ_EAGER && sched != SVQ_LAZY) return fail(SVQ_EINVAL, "bad schedule");
+    if (tile_k != 0 && (tile_k < 8 || tile_k > 13)) return fail(SVQ_EINVAL, "tile_k must be 0 or in [8, 13]");
+    std::vector<GateN> gn;
+    std::string err = normalize_gates(st->n, gates, m, n_theta, gn);
+    if (!err.empty()) return fail(SVQ_EINVAL, err);
+    s = check_theta(gn, theta, n_theta);
+    if (s) return s;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (m == 0) return SVQ_OK;
+    const int k = tile_k ? std::min(tile_k, st->n - st->g) : default_k(st);
+    const int c = default_c(st);
+    const int rb = gate_rb(k);
+    // host plan, cached on the handle (host memory only)
+    const std::string key = circuit_key(gn, st, sched, k, c, rb, false);
+    auto it = st->hcache.find(key);
+    HostCircuit *hc = nullptr;
+    if (it != st->hcache.end()) {
+        hc = it->second.get();
+    } else {
+        auto t0 = std::chrono::steady_clock::now();
+        auto h = std::make_unique<HostCircuit>();
+        err = plan_circuit(st->n, st->g, gn, sched, k, rb, c, st->pos, h->plan);
+        if (!err.empty()) return fail(SVQ_EINVAL, err);
+        h->json = std::make_shared<const std::string>(circuit_json(h->plan, sched, false));
+        if (stats)
+            stats->ms_plan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (st->hcache.size() > 64) st->hcache.clear();
+        hc = h.get();
+        st->hcache[key] = std::move(h);
+    }
+    const CircuitPlan &P = hc->plan;
+    // tables in the static scratch: phases, then ops at a 256-byte boundary
+    const size_t ph_bytes = sizeof(PhaseDesc) * P.phases.size();
+    const size_t op_off = (ph_bytes + 255) & ~(size_t)255;
+    const size_t need = op_off + sizeof(OpDesc) * P.ops.size();
+    if (need > kStaticScratchBytes)
+        return fail(SVQ_ESHAPE, "circuit tables need " + std::to_string(need) +
+                                    " bytes of static scratch; the limit is " +
+                                    std::to_string(kStaticScratchBytes));
+    void *scr = nullptr;
+    s = static_scratch(st, &scr);
+    if (s) return s;
+    std::vector<OpDesc> ops = P.ops;
+    fill_ops(gn, theta, P.op_gate, ops, false);
+    char *base = (char *)scr;
+    HIPCHK(st, hipMemcpyAsync(base, P.phases.data(), ph_bytes, hipMemcpyHostToDevice, st->stream),
+           "upload phases");
+    HIPCHK(st, hipMemcpyAsync(base + op_off, ops.data(), sizeof(OpDesc) * ops.size(),
+                              hipMemcpyHostToDevice, st->stream),
+           "upload ops");
+    st->last_plan = hc->json;
+    return run_circuit_steps(st, P, (const PhaseDesc *)base, (const OpDesc *)(base + op_off), stats);
 }
 
 svq_status sv_qr_permute(svq_state st, const int32_t *new_pos) {
