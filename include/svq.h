@@ -132,7 +132,9 @@ svq_status sv_get_amplitudes(svq_state st, void *host_logical);
  * sv_grad's circuit plan) as JSON text, for inspection and tests: schedule,
  * tile width k, low bits c, QR count (eq. n_qr), the schedule order, and the
  * steps in launch order -- {"type":"qr","swaps":[[a,b],...]} with physical bit
- * pairs, {"type":"gate_pass","tile_bits":[...],"gates":G,"phases":F} or
+ * pairs, {"type":"gate_pass","tile_bits":[...],"tile_bits_out":[...],
+ * "gates":G,"phases":F} (tile bit j is read from physical position
+ * tile_bits[j] and written to tile_bits_out[j]) or
  * {"type":"pauli_pass","tile_bits":[...],"groups":X} -- plus the layouts
  * before and after.  "{}" before any plan ran.  *len_out (nullable) receives
  * the size including the terminating NUL; json_buf may be NULL to query it.
@@ -236,6 +238,12 @@ svq_status sv_plan_circuit(int n, int g, const svq_gate *gates, int m, svq_sched
                            int tile_k, int32_t *order_out, int32_t *qr_tile_out,
                            int32_t *pass_out, uint64_t *local_out, int32_t *n_qr_out,
                            int32_t *n_pass_out);
+/* The same plan as sv_plan_circuit (initial layout pos[q] = q, low bits from
+ * SVQ_LOW_BITS, default 4) as the JSON text of sv_plan_dump, including each
+ * gate pass's store positions "tile_bits_out".  Host only.  Errors: EINVAL,
+ * ESHAPE (cap too small). */
+svq_status sv_plan_circuit_json(int n, int g, const svq_gate *gates, int m, svq_sched sched,
+                                int tile_k, char *json_buf, size_t cap, size_t *len_out);
 svq_status sv_plan_paulis(int n, int g, const svq_pauli *terms, int n_terms, svq_sched sched,
                           int tile_k, int32_t *order_out, int32_t *qr_tile_out,
                           int32_t *pass_out, uint64_t *local_out, int32_t *n_qr_out,

@@ -53,7 +53,7 @@ EXPORTS = ("sv_create", "sv_destroy", "sv_set_basis", "sv_set_amplitudes", "sv_g
            "sv_get_layout", "sv_plan_dump", "sv_device_ptr", "sv_apply_circuit",
            "sv_apply_circuit_static", "sv_qr_permute",
            "sv_expectation", "sv_expectation_qsu", "sv_apply_hamiltonian", "sv_grad", "sv_plan_circuit",
-           "sv_plan_paulis", "sv_plan_ops", "sv_tune_circuit", "sv_tune_paulis",
+           "sv_plan_circuit_json", "sv_plan_paulis", "sv_plan_ops", "sv_tune_circuit", "sv_tune_paulis",
            "sv_batch_tune", "sv_tune_save", "sv_tune_load", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
            "sv_batch_destroy", "sv_last_error")
 
@@ -87,6 +87,8 @@ def _load():
     L.sv_plan_circuit.argtypes = [c_int, c_int, POINTER(svq_gate), c_int, c_int, c_int,
                                   POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                   POINTER(c_uint64), POINTER(c_int32), POINTER(c_int32)]
+    L.sv_plan_circuit_json.argtypes = [c_int, c_int, POINTER(svq_gate), c_int, c_int, c_int,
+                                       ctypes.c_char_p, c_size_t, POINTER(c_size_t)]
     L.sv_plan_paulis.argtypes = [c_int, c_int, POINTER(svq_pauli), c_int, c_int, c_int,
                                  POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                  POINTER(c_uint64), POINTER(c_int32), POINTER(c_int32)]
@@ -298,6 +300,17 @@ def sv_plan_circuit(n, g, gates, sched, tile_k=0):
                                byref(npass)))
     return dict(order=list(order)[:m], qr_tile=list(qt)[:m], pass_=list(ps)[:m],
                 local=list(loc)[:m], n_qr=nqr.value, n_pass=npass.value)
+
+
+def sv_plan_circuit_json(n, g, gates, sched, tile_k=0):
+    """Host-only plan of a gate list, parsed from the library's JSON."""
+    import json
+    gc = gates_array(gates)
+    need = c_size_t(0)
+    _check(lib.sv_plan_circuit_json(n, g, gc, len(gates), sched, tile_k, None, 0, byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib.sv_plan_circuit_json(n, g, gc, len(gates), sched, tile_k, buf, need.value, None))
+    return json.loads(buf.value.decode())
 
 
 def sv_tune_circuit(h, gates_c, m, theta, n_theta, sched):

@@ -89,7 +89,8 @@ void json_qr(std::string &o, const std::vector<Transposition> &tr) {
     o += "]}";
 }
 
-void json_bits(std::string &o, const int8_t *bits, int nb) {
+template <typename T>
+void json_bits(std::string &o, const T *bits, int nb) {
     o += "[";
     for (int j = 0; j < nb; ++j) {
         if (j) o += ",";
@@ -122,6 +123,8 @@ std::string circuit_json(const CircuitPlan &P, svq_sched sched, bool adj) {
         const PassArgs &a = P.passes[s.idx];
         o += "{\"type\":\"gate_pass\",\"pass\":" + std::to_string(s.idx) + ",\"tile_bits\":";
         json_bits(o, a.tphys, P.k);
+        o += ",\"tile_bits_out\":";
+        json_bits(o, a.tphys_out, P.k);
         o += ",\"gates\":" + std::to_string(gates_in_pass[s.idx]);
         o += ",\"phases\":" + std::to_string(a.nphase) + "}";
     }
@@ -170,6 +173,10 @@ int env_int(const char *name, int dflt) {
     if (!v || !*v) return dflt;
     return std::atoi(v);
 }
+
+// Gate passes relabel their tile's positions on store (PassArgs::tphys_out)
+// unless SVQ_RELAYOUT=0.
+bool relayout_on() { return env_int("SVQ_RELAYOUT", 1) != 0; }
 
 }  // namespace
 
@@ -467,7 +474,7 @@ std::string circuit_key(const std::vector<GateN> &gates, const svq_state_s *st, 
                         int k, int c, int rb, bool adj) {
     std::string key;
     auto put = [&](const void *p, size_t nb) { key.append((const char *)p, nb); };
-    int hdr[7] = {st->n, st->g, (int)sched, k, c, rb, adj ? 1 : 0};
+    int hdr[8] = {st->n, st->g, (int)sched, k, c, rb, adj ? 1 : 0, relayout_on() ? 1 : 0};
     put(hdr, sizeof(hdr));
     for (int p : st->pos) put(&p, sizeof(p));
     for (const auto &g : gates) {
@@ -480,7 +487,7 @@ std::string circuit_key(const std::vector<GateN> &gates, const svq_state_s *st, 
 svq_status get_circuit_plan(svq_state st, const std::vector<GateN> &gates, svq_sched sched,
                             int k, bool adj, CachedCircuit **out, double *ms_plan) {
     const int c = default_c(st);
-    const int rb = gate_rb(k);
+    const int rb = gate_rb(k, st->dbl(), adj);
     std::string key = circuit_key(gates, st, sched, k, c, rb, adj);
     auto it = st->ccache.find(key);
     if (it != st->ccache.end()) {
@@ -490,7 +497,8 @@ svq_status get_circuit_plan(svq_state st, const std::vector<GateN> &gates, svq_s
     }
     auto t0 = std::chrono::steady_clock::now();
     auto cc = std::make_unique<CachedCircuit>();
-    std::string err = plan_circuit(st->n, st->g, gates, sched, k, rb, c, st->pos, cc->plan);
+    std::string err = plan_circuit(st->n, st->g, gates, sched, k, rb, c, st->pos, cc->plan,
+                                   relayout_on());
     if (!err.empty()) return fail(SVQ_EINVAL, err);
     auto t1 = std::chrono::steady_clock::now();
     *ms_plan = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -537,7 +545,7 @@ svq_status run_circuit_steps(svq_state st, const CircuitPlan &P, const PhaseDesc
         } else {
             const PassArgs &a = P.passes[s.idx];
             ProfScope ps(st, 0);
-            HIPCHK(st, launch_gate_pass(st->dbl(), P.k, false, st->buf, nullptr, a, phases_dev,
+            HIPCHK(st, launch_gate_pass(st->dbl(), P.k, P.rb, false, st->buf, nullptr, a, phases_dev,
                                         ops_dev, nullptr, a.nblocks, st->stream),
                    "gate_pass");
             bytes += 2.0 * (double)st->bytes();
@@ -896,7 +904,7 @@ svq_status sv_apply_circuit_static(svq_state st, const svq_gate *gates, int m, c
     if (m == 0) return SVQ_OK;
     const int k = tile_k ? std::min(tile_k, st->n - st->g) : default_k(st);
     const int c = default_c(st);
-    const int rb = gate_rb(k);
+    const int rb = gate_rb(k, st->dbl(), false);
     // host plan, cached on the handle (host memory only)
     const std::string key = circuit_key(gn, st, sched, k, c, rb, false);
     auto it = st->hcache.find(key);
@@ -906,7 +914,7 @@ svq_status sv_apply_circuit_static(svq_state st, const svq_gate *gates, int m, c
     } else {
         auto t0 = std::chrono::steady_clock::now();
         auto h = std::make_unique<HostCircuit>();
-        err = plan_circuit(st->n, st->g, gn, sched, k, rb, c, st->pos, h->plan);
+        err = plan_circuit(st->n, st->g, gn, sched, k, rb, c, st->pos, h->plan, relayout_on());
         if (!err.empty()) return fail(SVQ_EINVAL, err);
         h->json = std::make_shared<const std::string>(circuit_json(h->plan, sched, false));
         if (stats)
@@ -1154,7 +1162,7 @@ svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *the
             const PassArgs &a = P.passes[it->idx];
             {
                 ProfScope ps(st, 4);
-                HIPCHK(st, launch_gate_pass(st->dbl(), P.k, true, st->buf, st->d_lam.p, a,
+                HIPCHK(st, launch_gate_pass(st->dbl(), P.k, P.rb, true, st->buf, st->d_lam.p, a,
                                             (const PhaseDesc *)cc->d_phases.p,
                                             (const OpDesc *)st->d_ops.p, (double *)st->d_gpart.p,
                                             (int)nblocks, st->stream),
@@ -1198,8 +1206,22 @@ static svq_status plan_common_circuit(int n, int g, const svq_gate *gates, int m
     for (int q = 0; q < n; ++q) pos[q] = q;
     int k = tile_k ? tile_k : 12;
     k = std::max(8, std::min(13, std::min(k, n - g)));
-    err = plan_circuit(n, g, gn, sched, k, gate_rb(k), env_int("SVQ_LOW_BITS", 4), pos, P);
+    err = plan_circuit(n, g, gn, sched, k, gate_rb(k), env_int("SVQ_LOW_BITS", 4), pos, P,
+                       relayout_on());
     if (!err.empty()) return fail(SVQ_EINVAL, err);
+    return SVQ_OK;
+}
+
+svq_status sv_plan_circuit_json(int n, int g, const svq_gate *gates, int m, svq_sched sched,
+                                int tile_k, char *json_buf, size_t cap, size_t *len_out) {
+    CircuitPlan P;
+    svq_status s = plan_common_circuit(n, g, gates, m, sched, tile_k, P);
+    if (s) return s;
+    const std::string j = circuit_json(P, sched, false);
+    if (len_out) *len_out = j.size() + 1;
+    if (!json_buf) return SVQ_OK;
+    if (cap < j.size() + 1) return fail(SVQ_ESHAPE, "json_buf smaller than the plan text");
+    std::memcpy(json_buf, j.c_str(), j.size() + 1);
     return SVQ_OK;
 }
 
@@ -1383,7 +1405,7 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
         std::vector<int> pos(n);
         for (int q = 0; q < n; ++q) pos[q] = q;
         CircuitPlan cp;
-        err = plan_circuit(n, 0, gn, SVQ_LAZY, K, gate_rb(K), c, pos, cp);
+        err = plan_circuit(n, 0, gn, SVQ_LAZY, K, gate_rb(K), c, pos, cp, false);
         if (!err.empty()) return fail(SVQ_EINVAL, err);
         PauliPlan pp;
         err = plan_paulis(n, 0, terms[i], n_terms[i], SVQ_LAZY, K, c, false, pos, pp);

@@ -502,14 +502,19 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
     const int np = a.nphase;
     const PhaseDesc &P0 = phases[a.phase0 + (ADJ ? np - 1 : 0)];   // load mapping
     const PhaseDesc &PL = phases[a.phase0 + (ADJ ? 0 : np - 1)];   // store mapping
+    // The pass reads its tile with positions tphys and writes it with
+    // tphys_out (a permutation of the same positions); the reverse pass runs
+    // it backwards.
+    const int32_t *tp_in = ADJ ? a.tphys_out : a.tphys;
+    const int32_t *tp_out = ADJ ? a.tphys : a.tphys_out;
     const uint64_t base = spread(tile, a.tphys, K);
     Regs<R, NR> v, w;
     uint32_t sw;
     RegMap<RB, K> mc;
     {
         uint32_t tp0;
-        thread_maps<NWB, K>(P0, a.tphys, lane, wave, tp0, sw);
-        mc.init(P0, a.tphys);
+        thread_maps<NWB, K>(P0, tp_in, lane, wave, tp0, sw);
+        mc.init(P0, tp_in);
         load_regs<V, R, NR, RB, K, OFF32>(v, psi + base, tp0, mc);
         if constexpr (ADJ) load_regs<V, R, NR, RB, K, OFF32>(w, lam + base, tp0, mc);
     }
@@ -579,10 +584,10 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
         }
     }
     uint32_t tpL, tsL;
-    thread_maps<NWB, K>(PL, a.tphys, lane, wave, tpL, tsL);
+    thread_maps<NWB, K>(PL, tp_out, lane, wave, tpL, tsL);
     (void)tsL;
     RegMap<RB, K> mL;
-    mL.init(PL, a.tphys);
+    mL.init(PL, tp_out);
     store_regs<V, R, NR, RB, K, OFF32>(v, psi + base, tpL, mL);
     if constexpr (ADJ) {
         store_regs<V, R, NR, RB, K, OFF32>(w, lam + base, tpL, mL);
@@ -1188,11 +1193,10 @@ static int num_cu() {
     return g_num_cu;
 }
 
-template <typename R, int KK, bool ADJ>
-static hipError_t launch_gate_k(void *psi, void *lam, const PassArgs &a, const PhaseDesc *ph,
-                                const OpDesc *ops, double *gpart, hipStream_t s) {
+template <typename R, int KK, int RB, bool ADJ>
+static hipError_t launch_gate_kr(void *psi, void *lam, const PassArgs &a, const PhaseDesc *ph,
+                                 const OpDesc *ops, double *gpart, hipStream_t s) {
     using V = typename V2T<R>::type;
-    constexpr int RB = gate_rb(KK);
     constexpr int NT = 1 << (KK - RB);
     if constexpr (sizeof(R) * 2 * (ADJ ? 2 : 1) * (1 << KK) > 160 * 1024) {
         return hipErrorInvalidValue;
@@ -1210,13 +1214,28 @@ static hipError_t launch_gate_k(void *psi, void *lam, const PassArgs &a, const P
     }
 }
 
+// The plan fixes the register bits: a forward pass runs either its own width
+// or (inside sv_grad, on the adjoint's plan) the adjoint's.
+template <typename R, int KK, bool ADJ>
+static hipError_t launch_gate_k(int rb, void *psi, void *lam, const PassArgs &a,
+                                const PhaseDesc *ph, const OpDesc *ops, double *gpart,
+                                hipStream_t s) {
+    constexpr int RB_OWN = gate_rb(KK, sizeof(R) == 8, ADJ);
+    constexpr int RB_ADJ = gate_rb(KK, sizeof(R) == 8, true);
+    if (rb == RB_OWN) return launch_gate_kr<R, KK, RB_OWN, ADJ>(psi, lam, a, ph, ops, gpart, s);
+    if constexpr (RB_ADJ != RB_OWN) {
+        if (rb == RB_ADJ) return launch_gate_kr<R, KK, RB_ADJ, ADJ>(psi, lam, a, ph, ops, gpart, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename R>
-static hipError_t launch_gate_t(int k, bool adj, void *psi, void *lam, const PassArgs &a,
+static hipError_t launch_gate_t(int k, int rb, bool adj, void *psi, void *lam, const PassArgs &a,
                                 const PhaseDesc *ph, const OpDesc *ops, double *gpart, hipStream_t s) {
 #define SVQ_GATE_CASE(KK)                                                                   \
     case KK:                                                                                \
-        return adj ? launch_gate_k<R, KK, true>(psi, lam, a, ph, ops, gpart, s)             \
-                   : launch_gate_k<R, KK, false>(psi, lam, a, ph, ops, gpart, s);
+        return adj ? launch_gate_k<R, KK, true>(rb, psi, lam, a, ph, ops, gpart, s)         \
+                   : launch_gate_k<R, KK, false>(rb, psi, lam, a, ph, ops, gpart, s);
     switch (k) {
         SVQ_GATE_CASE(8)
         SVQ_GATE_CASE(9)
@@ -1230,12 +1249,12 @@ static hipError_t launch_gate_t(int k, bool adj, void *psi, void *lam, const Pas
 #undef SVQ_GATE_CASE
 }
 
-hipError_t launch_gate_pass(bool dbl, int k, bool adj, void *psi, void *lam, const PassArgs &a,
-                            const PhaseDesc *ph, const OpDesc *ops, double *gpart, int nbt,
-                            hipStream_t s) {
+hipError_t launch_gate_pass(bool dbl, int k, int rb, bool adj, void *psi, void *lam,
+                            const PassArgs &a, const PhaseDesc *ph, const OpDesc *ops,
+                            double *gpart, int nbt, hipStream_t s) {
     (void)nbt;
-    return dbl ? launch_gate_t<double>(k, adj, psi, lam, a, ph, ops, gpart, s)
-               : launch_gate_t<float>(k, adj, psi, lam, a, ph, ops, gpart, s);
+    return dbl ? launch_gate_t<double>(k, rb, adj, psi, lam, a, ph, ops, gpart, s)
+               : launch_gate_t<float>(k, rb, adj, psi, lam, a, ph, ops, gpart, s);
 }
 
 hipError_t launch_qr(bool dbl, void *psi, const QrArgs &a, hipStream_t s) {

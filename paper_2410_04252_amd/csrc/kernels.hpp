@@ -29,7 +29,8 @@ struct WideTerm {
     int32_t pad;
 };
 
-hipError_t launch_gate_pass(bool dbl, int k, bool adj, void *psi, void *lam, const PassArgs &a,
+// rb: the register bits the plan was built for (CircuitPlan::rb).
+hipError_t launch_gate_pass(bool dbl, int k, int rb, bool adj, void *psi, void *lam, const PassArgs &a,
                             const PhaseDesc *ph, const OpDesc *ops, double *gpart, int nbt,
                             hipStream_t s);
 hipError_t launch_qr(bool dbl, void *psi, const QrArgs &a, hipStream_t s);

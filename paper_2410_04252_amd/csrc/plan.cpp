@@ -257,6 +257,109 @@ static uint64_t choose_pass_set(uint64_t universe, uint64_t forced, const std::v
     return Gb.size() > Ga.size() ? b : a;
 }
 
+// ---- level 2 with a relabelling store ---------------------------------------
+// A pass may store its tile with the tile's bit positions permuted (in place:
+// the tile occupies the same addresses).  The previous pass's store therefore
+// moves c qubits that the next pass acts on into the c lowest physical
+// positions, which every tile must contain for coalescing; the next pass's
+// qubit set S (k qubits) then needs at most k - c qubits outside the previous
+// pass's set kprev.
+
+static bool rl_fits(uint64_t S, uint64_t kprev, int k, int c) {
+    return popc(S) <= k && popc(S & ~kprev) <= k - c;
+}
+
+// Complete S to k qubits: first from kprev (free under the k - c budget),
+// then from the other local qubits, each in ascending physical position.
+static uint64_t rl_fill(uint64_t S, uint64_t universe, uint64_t kprev, int k, int c,
+                        const std::vector<int> &lay) {
+    std::vector<int> qs;
+    for (uint64_t u = universe & ~S; u; u &= u - 1) qs.push_back(__builtin_ctzll(u));
+    std::sort(qs.begin(), qs.end(), [&](int a, int b) { return lay[a] < lay[b]; });
+    for (int pass = 0; pass < 2; ++pass)
+        for (int q : qs) {
+            if (popc(S) >= k) return S;
+            const bool inprev = (kprev >> q) & 1;
+            if ((pass == 0) != inprev || ((S >> q) & 1)) continue;
+            if (rl_fits(S | bit(q), kprev, k, c)) S |= bit(q);
+        }
+    return S;
+}
+
+// The two greedy candidates of pass_candidates under the relabelling
+// constraint (logical qubit sets).
+static void rl_candidates(uint64_t universe, uint64_t kprev, const std::vector<int> &remain,
+                          const std::vector<uint64_t> &targets, int k, int c,
+                          const std::vector<int> &lay, uint64_t &a, uint64_t &b) {
+    uint64_t avail = universe, S = 0;
+    for (int i : remain) {
+        const uint64_t T = targets[i];
+        if ((T & ~avail) == 0 && rl_fits(S | T, kprev, k, c)) S |= T;
+        else avail &= ~T;
+        if (!avail) break;
+    }
+    a = rl_fill(S, universe, kprev, k, c, lay);
+    S = 0;
+    for (;;) {
+        uint64_t av = S, blocked = 0;
+        int pick = -1, pick_new = 99;
+        for (int i : remain) {
+            const uint64_t T = targets[i];
+            if ((T & ~av) == 0) continue;
+            av &= ~T;
+            const bool frontier = (T & blocked) == 0;
+            blocked |= T;
+            if (!frontier) continue;
+            const int nw = popc(T & ~S);
+            if (nw > 0 && rl_fits(S | T, kprev, k, c) && nw < pick_new) {
+                pick = i;
+                pick_new = nw;
+            }
+        }
+        if (pick < 0) break;
+        S |= targets[pick];
+    }
+    b = rl_fill(S, universe, kprev, k, c, lay);
+}
+
+static uint64_t rl_fuller(uint64_t universe, uint64_t kprev, const std::vector<int> &remain,
+                          const std::vector<uint64_t> &targets, int k, int c,
+                          const std::vector<int> &lay) {
+    uint64_t a, b;
+    rl_candidates(universe, kprev, remain, targets, k, c, lay, a, b);
+    return tile_construction(b, remain, targets).size() > tile_construction(a, remain, targets).size()
+               ? b : a;
+}
+
+// Choose between the candidates by completing each greedily (the pass after
+// a pass with qubit set S has kprev = S) and counting passes.
+static uint64_t rl_choose(uint64_t universe, uint64_t kprev, const std::vector<int> &remain,
+                          const std::vector<uint64_t> &targets, int k, int c,
+                          const std::vector<int> &lay) {
+    uint64_t a, b;
+    rl_candidates(universe, kprev, remain, targets, k, c, lay, a, b);
+    const std::vector<int> Ga = tile_construction(a, remain, targets);
+    const std::vector<int> Gb = tile_construction(b, remain, targets);
+    if (a == b || Gb.empty()) return a;
+    if (Ga.empty()) return b;
+    const int m = (int)targets.size();
+    auto rollout = [&](std::vector<int> rest, uint64_t kp) {
+        int passes = 0;
+        while (!rest.empty()) {
+            const uint64_t S = rl_fuller(universe, kp, rest, targets, k, c, lay);
+            const std::vector<int> G = tile_construction(S, rest, targets);
+            if (G.empty()) return 1 << 20;
+            rest = without(rest, G, m);
+            kp = S;
+            ++passes;
+        }
+        return passes;
+    };
+    const int pa = rollout(without(remain, Ga, m), a), pb = rollout(without(remain, Gb, m), b);
+    if (pa != pb) return pa < pb ? a : b;
+    return Gb.size() > Ga.size() ? b : a;
+}
+
 static uint64_t local_set(const std::vector<int> &pos, int nL) {
     uint64_t s = 0;
     for (size_t q = 0; q < pos.size(); ++q)
@@ -576,15 +679,44 @@ static int op_type_of(int kind) {
     }
 }
 
-// Canonical load/store mapping: lanes are tile bits 0..5 (coalesced), the
-// registers are the highest RB tile bits.
-static uint32_t canonical_regs(int k, int rb) {
-    uint32_t r = 0;
-    for (int b = k - rb; b < k; ++b) r |= 1u << b;
-    return r;
+// Lanes of a load or store phase: the required tile bits (those on the
+// lowest physical positions, in position order, so that consecutive lanes
+// address consecutive amplitudes), then free bits preferring residue i mod 6
+// for lane i (distinct LDS banks under the swizzle).
+static void io_lanes(int k, uint32_t regs, const int *req, int nreq, PhaseDesc &D) {
+    int lanes[6] = {-1, -1, -1, -1, -1, -1};
+    uint32_t taken = regs;
+    for (int i = 0; i < nreq && i < 6; ++i) {
+        lanes[i] = req[i];
+        taken |= 1u << req[i];
+    }
+    for (int i = std::min(nreq, 6); i < 6; ++i)
+        for (int b = 0; b < k; ++b)
+            if (!((taken >> b) & 1) && b % 6 == i) {
+                lanes[i] = b;
+                taken |= 1u << b;
+                break;
+            }
+    for (int i = 0; i < 6; ++i)
+        if (lanes[i] < 0)
+            for (int b = 0; b < k; ++b)
+                if (!((taken >> b) & 1)) {
+                    lanes[i] = b;
+                    taken |= 1u << b;
+                    break;
+                }
+    for (int i = 0; i < 8; ++i) D.lane[i] = 0;
+    for (int i = 0; i < 6; ++i) D.lane[i] = lanes[i];
+    int nw = 0;
+    for (int i = 0; i < 8; ++i) D.wave[i] = 0;
+    for (int b = 0; b < k; ++b)
+        if (!((taken >> b) & 1)) D.wave[nw++] = b;
 }
 
-static void plan_phases(int k, int rb, const std::vector<L3Gate> &gs, CircuitPlan &P) {
+// Level 3.  ld/st: the tile bits the load and store phases must have as
+// lanes 0.. (in order).  They differ when the pass's store relabels positions.
+static void plan_phases(int k, int rb, const std::vector<L3Gate> &gs, CircuitPlan &P,
+                        const int *ld, int nld, const int *st, int nst) {
     const uint32_t all = (k >= 32) ? ~0u : ((1u << k) - 1);
     const uint32_t low6 = 63u;
     (void)low6;
@@ -663,50 +795,40 @@ static void plan_phases(int k, int rb, const std::vector<L3Gate> &gs, CircuitPla
             phs.push_back({(uint32_t)regs, G});
         }
     }
-    // A load/store phase needs lanes on tile bits 0..3 (the c = 4 forced low
-    // physical bits: 16 lanes cover one 128-byte run); its registers may use
-    // any of the other bits.
-    const uint32_t canon = canonical_regs(k, rb);
-    const uint32_t low4 = 15u;
-    auto lanes_ok = [&](uint32_t regs) { return (regs & low4) == 0; };
-    if (phs.empty() || !lanes_ok(phs.front().regs)) phs.insert(phs.begin(), Ph{canon, {}});
-    if (!lanes_ok(phs.back().regs)) phs.push_back(Ph{canon, {}});
-    for (auto &ph : phs) {
+    // The load phase needs lanes on the tile bits that sit on the lowest
+    // physical positions before the pass, the store phase on those that sit
+    // there after it; their registers may use any other bits.  A pure
+    // transpose phase is added where the first or last gate phase does not
+    // allow it (and whenever the two lane sets differ but one phase would do
+    // both).
+    uint32_t ldm = 0, stm = 0;
+    for (int i = 0; i < nld; ++i) ldm |= 1u << ld[i];
+    for (int i = 0; i < nst; ++i) stm |= 1u << st[i];
+    bool same_io = nld == nst;
+    for (int i = 0; same_io && i < nld; ++i) same_io = ld[i] == st[i];
+    auto io_regs = [&](uint32_t avoid) {
+        uint32_t r = 0;
+        for (int b = k - 1; b >= 0 && popc(r) < rb; --b)
+            if (!((avoid >> b) & 1)) r |= 1u << b;
+        return r;
+    };
+    if (phs.empty() || (phs.front().regs & ldm)) phs.insert(phs.begin(), Ph{io_regs(ldm), {}});
+    if ((phs.back().regs & stm) || (phs.size() == 1 && !same_io)) phs.push_back(Ph{io_regs(stm), {}});
+    for (size_t pi = 0; pi < phs.size(); ++pi) {
+        auto &ph = phs[pi];
         PhaseDesc D;
         std::memset(&D, 0, sizeof(D));
         set_regs(ph.regs, rb, D);
-        if ((ph.regs & low6) == 0) {
-            // keep lanes on bits 0..5 (coalesced global access)
+        if (pi == 0) {
+            io_lanes(k, ph.regs, ld, nld, D);
+        } else if (pi + 1 == phs.size()) {
+            io_lanes(k, ph.regs, st, nst, D);
+        } else if ((ph.regs & low6) == 0) {
+            // keep lanes on bits 0..5
             for (int i = 0; i < 6; ++i) D.lane[i] = i;
             int nw = 0;
             for (int b = 6; b < k; ++b)
                 if (!((ph.regs >> b) & 1)) D.wave[nw++] = b;
-        } else if (lanes_ok(ph.regs)) {
-            // lanes on bits 0..3 plus two free bits, preferring residues 4 and
-            // 5 mod 6 so that the LDS swizzle keeps the lanes on distinct banks
-            int lanes[6] = {0, 1, 2, 3, -1, -1};
-            uint32_t taken = ph.regs | low4;
-            for (int want = 4; want <= 5; ++want)
-                for (int b = 4; b < k; ++b)
-                    if (!((taken >> b) & 1) && b % 6 == want) {
-                        lanes[want] = b;
-                        taken |= 1u << b;
-                        break;
-                    }
-            for (int i = 4; i < 6; ++i)
-                if (lanes[i] < 0)
-                    for (int b = 4; b < k; ++b)
-                        if (!((taken >> b) & 1)) {
-                            lanes[i] = b;
-                            taken |= 1u << b;
-                            break;
-                        }
-            for (int i = 0; i < 8; ++i) D.lane[i] = 0;
-            for (int i = 0; i < 6; ++i) D.lane[i] = lanes[i];
-            int nw = 0;
-            for (int i = 0; i < 8; ++i) D.wave[i] = 0;
-            for (int b = 0; b < k; ++b)
-                if (!((taken >> b) & 1)) D.wave[nw++] = b;
         } else {
             assign_lanes(k, ph.regs, D);
         }
@@ -734,7 +856,8 @@ static void plan_phases(int k, int rb, const std::vector<L3Gate> &gs, CircuitPla
 }
 
 std::string plan_circuit(int n, int g, const std::vector<GateN> &gates, svq_sched sched, int k,
-                         int rb, int c, const std::vector<int> &pos0, CircuitPlan &out) {
+                         int rb, int c, const std::vector<int> &pos0, CircuitPlan &out,
+                         bool relayout) {
     out = CircuitPlan();
     out.n = n;
     out.g = g;
@@ -755,77 +878,148 @@ std::string plan_circuit(int n, int g, const std::vector<GateN> &gates, svq_sche
     std::vector<L1Tile> tiles = (sched == SVQ_LAZY)
                                     ? flat_tiling(n, nL, targets, pos)
                                     : ad_hoc(n, nL, targets, depth_order(targets), pos);
-    out.pos_after = pos;
-    // replay layouts tile by tile for levels 2/3
+    (void)pos;
+    // Replay the layout tile by tile for levels 2/3.  The exchanged qubits of
+    // each QR come from level 1; their physical pairing (ascending positions)
+    // is taken on the replayed layout, since level 2 may relabel positions
+    // inside tiles.
     std::vector<int> lay = pos0;
     const uint64_t localpos = bit(nL) - 1;
     const uint64_t forced = bit(ceff) - 1;
+    const int cl = std::min(ceff, 6);   // lowest positions the lanes cover
     int qrtile = 0;
+    auto add_positions = [&](const std::vector<int> &G, const L1Tile &T) {
+        for (int i : G) {
+            out.order.push_back(i);
+            out.pos_qrtile.push_back(qrtile);
+            out.pos_pass.push_back((int)out.passes.size());
+            out.pos_local.push_back(T.local);
+        }
+    };
+    // level 3 of one pass; qin[j] is the logical qubit on tile bit j
+    auto level3 = [&](PassArgs &pa, const std::vector<int> &G, const std::vector<int> &qin) {
+        std::vector<int> tl(n, -1);
+        for (int j = 0; j < keff; ++j) tl[qin[j]] = j;
+        std::vector<L3Gate> l3;
+        for (int i : G) {
+            const GateN &gt = gates[i];
+            L3Gate x;
+            x.gate = i;
+            x.kind = gt.kind;
+            x.tq0 = tl[gt.q[0]];
+            x.tq1 = gt.nq > 1 ? tl[gt.q[1]] : -1;
+            x.t = (1u << x.tq0) | (x.tq1 >= 0 ? 1u << x.tq1 : 0u);
+            x.mix = x.t;   // every qubit of the gate is a register bit
+            x.ctrl = gt.ctrlmask ? 1u << x.tq0 : 0u;
+            x.diag = gt.diag_q >= 0 ? tl[gt.diag_q] : -1;
+            l3.push_back(x);
+        }
+        int ld[6], st[6], nld = 0, nst = 0;
+        if (relayout) {
+            for (int j = 0; j < keff; ++j)
+                if (pa.tphys[j] < cl) ld[nld++] = j;
+            for (int ppos = 0; ppos < cl; ++ppos)
+                for (int j = 0; j < keff; ++j)
+                    if (pa.tphys_out[j] == ppos) st[nst++] = j;
+        } else {
+            // tile bits 0..3 (16 lanes cover a 128-byte run)
+            for (int j = 0; j < 4 && j < keff; ++j) ld[nld++] = st[nst++] = j;
+        }
+        pa.phase0 = (int)out.phases.size();
+        plan_phases(keff, rb, l3, out, ld, nld, st, nst);
+        pa.nphase = (int)out.phases.size() - pa.phase0;
+    };
     for (const L1Tile &T : tiles) {
-        if (!T.qr.empty()) {
+        if (local_set(lay, nL) != T.local) {
             Step s;
             s.type = 0;
-            s.qr = T.qr;
+            s.qr = remap(lay, nL, T.local);
             out.steps.push_back(s);
             out.n_qr += 1;
-            for (const Transposition &tr : T.qr) {
-                for (int q = 0; q < n; ++q) {
-                    if (lay[q] == tr.a) lay[q] = tr.b;
-                    else if (lay[q] == tr.b) lay[q] = tr.a;
-                }
-            }
         }
-        // physical target masks for this tile
-        std::vector<uint64_t> pt(m, 0);
-        for (int i : T.ops) pt[i] = phys_mask(targets[i], lay);
+        if (!relayout) {
+            std::vector<uint64_t> pt(m, 0);
+            for (int i : T.ops) pt[i] = phys_mask(targets[i], lay);
+            std::vector<int> remain = T.ops;
+            while (!remain.empty()) {
+                const uint64_t S = choose_pass_set(localpos, forced, remain, pt, keff);
+                std::vector<int> G = tile_construction(S, remain, pt);
+                if (G.empty()) return "internal: empty gate pass";
+                remain = without(remain, G, m);
+                PassArgs pa;
+                std::memset(&pa, 0, sizeof(pa));
+                std::vector<int> qin(keff);
+                int j = 0;
+                for (uint64_t u = S; u; u &= u - 1, ++j) {
+                    pa.tphys[j] = pa.tphys_out[j] = __builtin_ctzll(u);
+                    for (int q = 0; q < n; ++q)
+                        if (lay[q] == pa.tphys[j]) qin[j] = q;
+                }
+                pa.nblocks = 1 << (n - keff);
+                level3(pa, G, qin);
+                Step s;
+                s.type = 1;
+                s.idx = (int)out.passes.size();
+                out.steps.push_back(s);
+                add_positions(G, T);
+                out.passes.push_back(pa);
+            }
+            ++qrtile;
+            continue;
+        }
+        // relabelling passes
+        uint64_t kprev = 0;
+        for (int q = 0; q < n; ++q)
+            if (lay[q] < ceff) kprev |= bit(q);
+        const int first = (int)out.passes.size();
+        std::vector<std::vector<int>> Gs, qins;
         std::vector<int> remain = T.ops;
         while (!remain.empty()) {
-            uint64_t S = choose_pass_set(localpos, forced, remain, pt, keff);
-            std::vector<int> G = tile_construction(S, remain, pt);
+            const uint64_t S = rl_choose(T.local, kprev, remain, targets, keff, ceff, lay);
+            std::vector<int> G = tile_construction(S, remain, targets);
             if (G.empty()) return "internal: empty gate pass";
-            std::vector<char> tk(m, 0);
-            for (int i : G) tk[i] = 1;
-            std::vector<int> rest;
-            for (int i : remain)
-                if (!tk[i]) rest.push_back(i);
-            remain.swap(rest);
-            // level 3
-            std::vector<L3Gate> l3;
-            for (int i : G) {
-                const GateN &gt = gates[i];
-                L3Gate x;
-                x.gate = i;
-                x.kind = gt.kind;
-                x.tq0 = first_bit(to_tile(bit(lay[gt.q[0]]), S));
-                x.tq1 = gt.nq > 1 ? first_bit(to_tile(bit(lay[gt.q[1]]), S)) : -1;
-                x.t = to_tile(pt[i], S);
-                x.mix = x.t;   // every qubit of the gate is a register bit
-                x.ctrl = to_tile(phys_mask(gt.ctrlmask, lay), S);
-                x.diag = gt.diag_q >= 0 ? first_bit(to_tile(bit(lay[gt.diag_q]), S)) : -1;
-                l3.push_back(x);
+            remain = without(remain, G, m);
+            if ((int)out.passes.size() > first) {
+                // the previous pass stores its qubits relabelled: those of S
+                // on its lowest positions (c of them on the c lowest), the
+                // others above
+                PassArgs &pp = out.passes.back();
+                const std::vector<int> &qp = qins.back();
+                std::vector<int> A, B;
+                for (int j = 0; j < keff; ++j) ((S >> qp[j]) & 1 ? A : B).push_back(qp[j]);
+                if ((int)A.size() < ceff) return "internal: relabelled pass lacks low qubits";
+                std::vector<int> order = A;
+                order.insert(order.end(), B.begin(), B.end());
+                for (int i = 0; i < keff; ++i) lay[order[i]] = pp.tphys[i];   // tphys ascending
+                for (int j = 0; j < keff; ++j) pp.tphys_out[j] = lay[qp[j]];
             }
+            const uint64_t Tm = phys_mask(S, lay);
+            if (popc(Tm) != keff || (Tm & forced) != forced || (Tm & ~localpos))
+                return "internal: relabelled tile misses the low positions";
             PassArgs pa;
             std::memset(&pa, 0, sizeof(pa));
+            std::vector<int> qin(keff);
             int j = 0;
-            for (uint64_t s = S; s; s &= s - 1) pa.tphys[j++] = (int8_t)__builtin_ctzll(s);
-            pa.phase0 = (int)out.phases.size();
-            plan_phases(keff, rb, l3, out);
-            pa.nphase = (int)out.phases.size() - pa.phase0;
+            for (uint64_t u = Tm; u; u &= u - 1, ++j) {
+                pa.tphys[j] = pa.tphys_out[j] = __builtin_ctzll(u);
+                for (int q = 0; q < n; ++q)
+                    if (lay[q] == pa.tphys[j]) qin[j] = q;
+            }
             pa.nblocks = 1 << (n - keff);
             Step s;
             s.type = 1;
             s.idx = (int)out.passes.size();
             out.steps.push_back(s);
-            for (int i : G) {
-                out.order.push_back(i);
-                out.pos_qrtile.push_back(qrtile);
-                out.pos_pass.push_back((int)out.passes.size());
-                out.pos_local.push_back(T.local);
-            }
+            add_positions(G, T);
             out.passes.push_back(pa);
+            Gs.push_back(G);
+            qins.push_back(qin);
+            kprev = S;
         }
+        for (size_t i = 0; i < Gs.size(); ++i) level3(out.passes[first + i], Gs[i], qins[i]);
         ++qrtile;
     }
+    out.pos_after = lay;
     return "";
 }
 

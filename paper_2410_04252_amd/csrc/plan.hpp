@@ -98,8 +98,12 @@ struct CircuitPlan {
     int n_phases_total = 0;
 };
 
+// relayout: passes may store their tile with its bit positions permuted
+// (PassArgs::tphys_out), so that the next pass's qubits sit on the c lowest
+// positions; otherwise every tile takes the c lowest positions as they are.
 std::string plan_circuit(int n, int g, const std::vector<GateN> &gates, svq_sched sched, int k,
-                         int rb, int c, const std::vector<int> &pos0, CircuitPlan &out);
+                         int rb, int c, const std::vector<int> &pos0, CircuitPlan &out,
+                         bool relayout = true);
 
 // Fill op coefficients for the given angles (forward).  For the adjoint sweep
 // `inverse` fills U^dagger and the generator data.

@@ -21,8 +21,14 @@ constexpr int kMaxTileBits = 14;
 constexpr int kLaneBits = 6;      // wave64
 
 // Register bits per thread of a gate pass over 2^k amplitudes (at least one
-// wave per tile).
-constexpr int gate_rb(int k) { return k - 6 < 4 ? k - 6 : 4; }
+// wave per tile).  A fifth bit cuts the phases (LDS transposes) of the
+// 30-qubit fabric plan by a fifth but doubles the amplitude registers, and
+// measured no faster; the streaming forward pass also holds the next tile.
+constexpr int gate_rb(int k, bool dbl = false, bool adj = false) {
+    (void)dbl;
+    (void)adj;
+    return k - 6 < 4 ? k - 6 : 4;
+}
 // Threads (log2) of a Pauli pass: every thread owns a 2^(k-1-tpb) cube of
 // the half space (EVC) or a 2^(k-tpb) cube of outputs (H|psi>).  Eight pairs
 // per thread keep twice as many waves resident per staged tile as sixteen
@@ -91,7 +97,13 @@ struct PassArgs {
     int32_t phase0;
     int32_t spare;
     int32_t nblocks;
-    int8_t tphys[16];     // physical bit of tile-local bit j (ascending)
+    // 32-bit entries: the kernels index them with phase-table values, which
+    // must stay scalar loads (a byte would be a vector load whose wait also
+    // waits for the tile's amplitude loads in flight).
+    int32_t tphys[16];     // physical bit of tile-local bit j when loaded (ascending)
+    int32_t tphys_out[16]; // physical bit of tile-local bit j when stored: a
+                           // permutation of tphys (the same addresses), so a
+                           // pass may relabel its tile's positions in place
 };
 
 // Read-only Pauli pass (EVC) and H|psi> pass.
