@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "QSU gates/s + HBM GB/s frac at 30q; EVC terms/s; adjoint vs param-shift grad/s"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gate_pass_fabric30.json")
+TRAFFIC_FILE_C128 = os.path.join(ROOT, "profiles", "traffic_gate_pass_fabric30_c128.json")
 
 
 def log(*a):
@@ -107,6 +108,7 @@ def measure_main(P, W, torch, args):
     gp_avg_ms = t_gp / max(1, n_gp)
     gp_bytes = 2.0 * S                     # one read + one write of the state per launch
     achieved = gp_bytes / (gp_avg_ms * 1e-3) / 1e9
+    evc_roof = evc_roofline(n, nt, t_ev / args.steps, dtype)
     if args.no_eager:
         st.close()
         return dict(
@@ -119,7 +121,7 @@ def measure_main(P, W, torch, args):
                      gate_pass_avg_ms=gp_avg_ms, qr_pass_avg_ms=t_qr / max(1, n_qr)),
             evc=dict(terms_per_s=nt / (evc_ms * 1e-3), ms=evc_ms, evc_passes=s2.n_evc_passes,
                      groups=s2.n_groups, qr_lazy=s2.n_qr, evc_pass_avg_ms=t_ev / max(1, n_ev),
-                     plan_ms=s2.ms_plan),
+                     plan_ms=s2.ms_plan, roofline=evc_roof),
             roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
                           kernel="k_gate_pass<float,%d,4,false,true>" % (s1.tile_k or 12),
@@ -164,7 +166,8 @@ def measure_main(P, W, torch, args):
         evc=dict(terms_per_s=nt / (evc_ms * 1e-3), ms=evc_ms, evc_passes=s2.n_evc_passes,
                  groups=s2.n_groups, qr_lazy=s2.n_qr, qr_eager=se2.n_qr, eager_ms=evc_eager_ms,
                  evc_pass_avg_ms=t_ev / max(1, n_ev), plan_ms=s2.ms_plan,
-                 read_gbs=s2.n_evc_passes * S / (max(1e-9, t_ev / max(1, args.steps)) * 1e-3) / 1e9),
+                 read_gbs=s2.n_evc_passes * S / (max(1e-9, t_ev / max(1, args.steps)) * 1e-3) / 1e9,
+                 roofline=evc_roof),
         qsu_evc=qsu_evc, tuned=tuned,
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
@@ -172,6 +175,25 @@ def measure_main(P, W, torch, args):
                       bytes_per_launch=gp_bytes, launches=n_gp, avg_ms=gp_avg_ms),
     )
     return out
+
+
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def evc_roofline(n, nt, evc_pass_ms_per_step, dtype):
+    """ALU roofline of the Pauli passes.  Algorithmic work: the direct
+    evaluation of eq. evc, each Pauli string over its 2^(n-1) amplitude pairs
+    (i, i xor x) with one complex product conj(psi_{i^x}) psi_i (6 flops) and
+    one signed accumulation (2 flops): 4 * 2^n flops per string.  The kernel
+    shares the products of a flip-mask group and the signs of its strings
+    (Walsh-Hadamard), so it executes fewer."""
+    flops = 4.0 * (1 << n) * nt
+    achieved = flops / (evc_pass_ms_per_step * 1e-3) / 1e12
+    peak = FP32_PEAK_TFLOPS if dtype == "c64" else FP64_PEAK_TFLOPS
+    return dict(bound="alu", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
+                frac=round(achieved / peak, 4), traffic=None, kernel="k_evc_pass",
+                flops_per_step=flops, pass_ms_per_step=evc_pass_ms_per_step)
 
 
 def measure_copy_gbs(torch):
@@ -261,17 +283,37 @@ def measure_c128(P, W, torch, args):
     st.close()
     S = (1 << n) * 16
     gp_avg = t_gp / max(1, n_gp)
-    qsu_ms = (t_gp + t_qr * s1.n_qr / max(1, s1.n_qr + s2.n_qr)) / reps
-    log(f"[bench] c128: gate pass {gp_avg:.2f} ms ({2 * S / (gp_avg * 1e-3) / 1e9:.0f} GB/s), "
+    qr_avg = t_qr / max(1, n_qr)
+    qsu_ms = (t_gp + qr_avg * s1.n_qr * reps) / reps
+    gbs = 2 * S / (gp_avg * 1e-3) / 1e9
+    log(f"[bench] c128: gate pass {gp_avg:.2f} ms ({gbs:.0f} GB/s), "
         f"{s1.n_gate_passes} passes; EVC passes {t_ev / reps:.1f} ms; E={e:.12f}")
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE_C128):
+        try:
+            tf = json.load(open(TRAFFIC_FILE_C128))
+            if tf.get("source_hash") == kernel_source_hash():
+                traffic = tf.get("bytes_per_launch")
+        except Exception:
+            traffic = None
     return dict(workload=args.workload, dtype="c128", gate_passes=s1.n_gate_passes, tile_k=s1.tile_k,
-                gate_pass_avg_ms=gp_avg, gate_pass_gbs=2 * S / (gp_avg * 1e-3) / 1e9,
-                gate_pass_hbm_frac=2 * S / (gp_avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                qsu_gates_per_s_kernels=m / (qsu_ms * 1e-3), evc_pass_ms=t_ev / reps,
-                evc_terms_per_s_kernels=nt / (t_ev / reps * 1e-3), energy=e)
+                qr_lazy=s1.n_qr, gate_pass_avg_ms=gp_avg, qr_pass_avg_ms=qr_avg,
+                qsu_ms_kernels=qsu_ms, qsu_gates_per_s_kernels=m / (qsu_ms * 1e-3),
+                evc_pass_ms=t_ev / reps, evc_terms_per_s_kernels=nt / (t_ev / reps * 1e-3),
+                energy=e,
+                roofline=dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=round(gbs / HBM_PEAK_GBS, 4), traffic=traffic,
+                              kernel="k_gate_pass<double,%d,4,false,true>" % (s1.tile_k or 12),
+                              bytes_per_launch=2 * S, launches=n_gp, avg_ms=gp_avg),
+                evc_roofline=evc_roofline(n, nt, t_ev / reps, "c128"))
 
 
 def measure_grad(P, W, torch, args):
+    """cfg: 24 qubits, 400 parameters, 1000 strings, complex64.  The adjoint
+    gradient (sv_grad) against the GPU parameter-shift driver
+    (sv_param_shift_grad) under the exact rules (two evaluations per CPHASE,
+    four per GIVENS) and under the nominal two evaluations per parameter."""
+    import numpy as np
     cfg = W.config("grad24")
     circ, ham = cfg["circuit"], cfg["ham"]
     n = circ.n
@@ -282,62 +324,174 @@ def measure_grad(P, W, torch, args):
     terms_c = P.paulis_array(ham)
     m, nt, npar = len(circ.gates), len(ham.coef), len(circ.theta)
     theta = circ.theta.copy()
+    S = (1 << n) * 8
     log(f"[bench] gradient workload grad24: n={n} params={npar} gates={m} terms={nt}")
     # adjoint
     P.sv_set_basis(h, circ.psi0_index)
     P.sv_grad(h, gates_c, m, theta, npar, terms_c, nt, P.LAZY)
     torch.cuda.synchronize()
     reps = 3
+    P.sv_profile(h, 1)
     t0 = time.perf_counter()
     for _ in range(reps):
         P.sv_set_basis(h, circ.psi0_index)
         e_adj, g_adj, sg = P.sv_grad(h, gates_c, m, theta, npar, terms_c, nt, P.LAZY)
     torch.cuda.synchronize()
     adj_ms = (time.perf_counter() - t0) * 1e3 / reps
-    # parameter shift on the GPU (exact rules: 2 evaluations for CPHASE, 4 for GIVENS)
-    r2 = math.sqrt(2.0)
-    rules = {"CPHASE": ((math.pi / 2, 0.5),),
-             "GIVENS": ((math.pi / 2, (r2 + 1) / (4 * r2)), (3 * math.pi / 2, -(r2 - 1) / (4 * r2)))}
-    kind_of = {}
-    for kind, qs, p in circ.gates:
-        kind_of[p] = kind
-    evals = []
-    for p in range(npar):
-        for shift, w in rules[kind_of[p]]:
-            evals.append((p, +shift, w))
-            evals.append((p, -shift, -w))
-    e_dev = torch.zeros(len(evals), dtype=torch.float64, device="cuda")
-    base = e_dev.data_ptr()
-
-    def run_shift(limit=None):
-        th = theta.copy()
-        for i, (p, s, _) in enumerate(evals[:limit]):
-            th[p] = theta[p] + s
-            P.sv_set_basis(h, circ.psi0_index)
-            P.sv_apply_circuit(h, gates_c, m, th, npar, P.LAZY, 0)
-            P.sv_expectation(h, terms_c, nt, P.LAZY, energy_dev=base + 8 * i, want_host=False)
-            th[p] = theta[p]
-
-    run_shift(8)   # warm plans
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run_shift()
-    torch.cuda.synchronize()
-    ps_ms = (time.perf_counter() - t0) * 1e3
-    ev = e_dev.cpu().numpy()
-    g_ps = [0.0] * npar
-    for (p, s, w), e in zip(evals, ev):
-        g_ps[p] += w * e
-    import numpy as np
-    g_ps = np.array(g_ps)
+    n_adj, t_adj = P.sv_profile_read(h, P.PROF_ADJ)
+    P.sv_profile(h, 0)
+    adj_avg = t_adj / max(1, n_adj)
+    adj_gbs = 4 * S / (adj_avg * 1e-3) / 1e9
+    # parameter shift on the GPU, exact rules and the nominal two-term rule
+    P.sv_set_basis(h, circ.psi0_index)
+    out = {}
+    for name, rule in (("exact", P.SHIFT_EXACT), ("two_term", P.SHIFT_TWO_TERM)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, g_ps, nev, _ = P.sv_param_shift_grad(h, gates_c, m, theta, npar, terms_c, nt, P.LAZY,
+                                                rule, want_energy=False)
+        torch.cuda.synchronize()
+        out[name] = ((time.perf_counter() - t0) * 1e3, nev, g_ps)
+    ps_ms, nev_exact, g_ps = out["exact"]
+    nominal_ms, nev_two, _ = out["two_term"]
     rel = float(np.linalg.norm(g_adj - g_ps) / max(1e-300, np.linalg.norm(g_ps)))
     st.close()
-    log(f"[bench] adjoint {adj_ms:.2f} ms/grad; param-shift {ps_ms:.1f} ms/grad "
-        f"({len(evals)} evaluations); rel diff {rel:.2e}")
-    return dict(workload="grad24", n=n, params=npar, terms=nt, adjoint_ms=adj_ms,
-                adjoint_grad_per_s=1e3 / adj_ms, param_shift_ms=ps_ms,
-                param_shift_grad_per_s=1e3 / ps_ms, param_shift_evaluations=len(evals),
-                speedup=ps_ms / adj_ms, rel_diff_adjoint_vs_shift=rel)
+    log(f"[bench] adjoint {adj_ms:.2f} ms/grad ({sg.bytes / (adj_ms * 1e-3) / 1e9:.0f} GB/s of "
+        f"algorithmic traffic; reverse pass {adj_avg:.2f} ms, {adj_gbs:.0f} GB/s); "
+        f"param-shift {ps_ms:.1f} ms/grad ({nev_exact} evaluations), nominal {nominal_ms:.1f} ms "
+        f"({nev_two}); rel diff {rel:.2e}")
+    return dict(workload="grad24", n=n, g=g, params=npar, terms=nt, adjoint_ms=adj_ms,
+                adjoint_grad_per_s=1e3 / adj_ms, adjoint_bytes=sg.bytes,
+                adjoint_gbs=sg.bytes / (adj_ms * 1e-3) / 1e9,
+                adjoint_roofline=dict(bound="hbm", achieved=round(adj_gbs, 1), peak=HBM_PEAK_GBS,
+                                      unit="GB/s", frac=round(adj_gbs / HBM_PEAK_GBS, 4),
+                                      kernel="k_gate_pass<float,k,4,true,true>",
+                                      bytes_per_launch=4 * S, launches=n_adj, avg_ms=adj_avg),
+                param_shift_ms=ps_ms, param_shift_grad_per_s=1e3 / ps_ms,
+                param_shift_evaluations=nev_exact,
+                param_shift_nominal_ms=nominal_ms, param_shift_nominal_evaluations=nev_two,
+                speedup=ps_ms / adj_ms, speedup_vs_nominal=nominal_ms / adj_ms,
+                rel_diff_adjoint_vs_shift=rel)
+
+
+def _qsu_evc_leg(P, torch, circ, ham, g, dtype, reps=2, with_eager=True, tile_k=0):
+    """Lazy QSU and EVC of one workload: kernel times from the library's
+    per-launch events, pass and QR counts; eager QR counts from the planner."""
+    n = circ.n
+    S = (1 << n) * (8 if dtype == "c64" else 16)
+    st = P.State(n, g, dtype)
+    h = st.h
+    gc, tc = P.gates_array(circ.gates), P.paulis_array(ham)
+    m, nt = len(circ.gates), len(ham.coef)
+
+    def once():
+        P.sv_set_basis(h, circ.psi0_index)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s1 = P.sv_apply_circuit(h, gc, m, circ.theta, len(circ.theta), P.LAZY, tile_k)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e, s2 = P.sv_expectation(h, tc, nt, P.LAZY)
+        t2 = time.perf_counter()
+        return s1, s2, e, (t1 - t0) * 1e3, (t2 - t1) * 1e3
+
+    once()
+    P.sv_profile(h, 1)
+    res = [once() for _ in range(reps)]
+    n_gp, t_gp = P.sv_profile_read(h, P.PROF_GATE)
+    n_qr, t_qr = P.sv_profile_read(h, P.PROF_QR)
+    n_ev, t_ev = P.sv_profile_read(h, P.PROF_EVC)
+    P.sv_profile(h, 0)
+    st.close()
+    s1, s2, e = res[-1][0], res[-1][1], res[-1][2]
+    qsu_ms = min(r[3] for r in res)
+    evc_ms = min(r[4] for r in res)
+    gp_avg = t_gp / max(1, n_gp)
+    out = dict(n=n, g=g, dtype=dtype, gates=m, terms=nt, energy=e,
+               qsu_ms=qsu_ms, gates_per_s=m / (qsu_ms * 1e-3), gate_passes=s1.n_gate_passes,
+               tile_k=s1.tile_k, qr_lazy=s1.n_qr, gate_pass_avg_ms=gp_avg,
+               gate_pass_gbs=2 * S / (gp_avg * 1e-3) / 1e9,
+               gate_pass_hbm_frac=2 * S / (gp_avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               qr_pass_avg_ms=t_qr / max(1, n_qr) if n_qr else None,
+               evc_ms=evc_ms, terms_per_s=nt / (evc_ms * 1e-3), evc_passes=s2.n_evc_passes,
+               evc_qr_lazy=s2.n_qr, evc_pass_avg_ms=t_ev / max(1, n_ev),
+               evc_roofline=evc_roofline(n, nt, t_ev / reps, dtype))
+    if with_eager:
+        out["qr_eager"] = P.sv_plan_circuit(n, g, circ.gates, P.EAGER, s1.tile_k)["n_qr"]
+        out["evc_qr_eager"] = P.sv_plan_paulis(n, g, ham, P.EAGER)["n_qr"]
+    return out
+
+
+def measure_legs(P, W, torch, args):
+    """The other configurations: the 12-qubit hardware-efficient ansatz
+    (complex128, lazy and eager, energy against the oracle), the 28-qubit
+    fabric (complex64) and the 32-qubit fabric (complex64 and complex128,
+    10^4 strings), whose energy is checked against the host oracle at reduced
+    depth (2 brick layers, 16 of the strings)."""
+    import numpy as np
+    import oracle
+    legs = {}
+    c = W.config("hea12")
+    e_ref = oracle.energy(c["circuit"], c["ham"])
+    hea = {}
+    for name, sched in (("lazy", P.LAZY), ("eager", P.EAGER)):
+        st = P.State(12, c["g"], "c128")
+        st.set_basis(0)
+        s1 = st.apply(c["circuit"], sched=sched, tile_k=c["k"])
+        e, s2 = st.expectation(c["ham"], sched=sched)
+        st.close()
+        hea[name] = dict(qr=s1.n_qr, gate_passes=s1.n_gate_passes, evc_qr=s2.n_qr,
+                         energy_abs_err=abs(e - e_ref))
+    legs["hea12"] = dict(n=12, g=c["g"], dtype="c128", tile_k=c["k"], energy_ref=e_ref, **hea)
+    log(f"[bench] hea12 c128: QR lazy {hea['lazy']['qr']} eager {hea['eager']['qr']}; "
+        f"|dE| {hea['lazy']['energy_abs_err']:.1e}")
+    c = W.config("fabric28")
+    legs["fabric28"] = _qsu_evc_leg(P, torch, c["circuit"], c["ham"], c["g"], "c64")
+    L = legs["fabric28"]
+    log(f"[bench] fabric28 c64: QSU {L['qsu_ms']:.1f} ms ({L['gates_per_s']:.0f} gates/s, "
+        f"{L['gate_passes']} passes, QR {L['qr_lazy']} vs eager {L['qr_eager']}), gate pass "
+        f"{L['gate_pass_gbs']:.0f} GB/s; EVC {L['evc_ms']:.1f} ms ({L['terms_per_s']:.0f} terms/s)")
+    if args.no_fabric32:
+        return legs
+    c = W.config("fabric32")
+    circ, ham, g = c["circuit"], c["ham"], c["g"]
+    f32 = {}
+    for dtype in ("c64", "c128"):
+        f32[dtype] = _qsu_evc_leg(P, torch, circ, ham, g, dtype, reps=1)
+        L = f32[dtype]
+        log(f"[bench] fabric32 {dtype}: QSU {L['qsu_ms']:.1f} ms ({L['gate_passes']} passes, QR "
+            f"{L['qr_lazy']} vs eager {L['qr_eager']}), gate pass {L['gate_pass_gbs']:.0f} GB/s; "
+            f"EVC {L['evc_ms']:.0f} ms ({L['terms_per_s']:.0f} terms/s, QR {L['evc_qr_lazy']} vs "
+            f"{L['evc_qr_eager']})")
+    # reduced depth against the oracle (2 layers of the same seeded ansatz)
+    short = W.fabric(32, 2, W.SEED_BASE + 3)
+    rng = np.random.default_rng(3232)
+    pick = np.sort(rng.choice(len(ham.coef), size=16, replace=False))
+    sub = W.Hamiltonian(32, ham.x[pick], ham.z[pick], ham.coef[pick])
+    e_gpu = {}
+    for dtype in ("c64", "c128"):
+        st = P.State(32, g, dtype)
+        st.set_basis(short.psi0_index)
+        st.apply(short)
+        e_gpu[dtype], _ = st.expectation(sub)
+        st.close()
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    log("[bench] fabric32 reduced depth: host oracle (2 layers, 2^32 complex128)")
+    psi = oracle.basis_state(32, short.psi0_index)
+    oracle.apply_circuit_inplace(psi, short.gates, short.theta)
+    e_ref = oracle.expectation(psi, sub)
+    del psi
+    scale = max(abs(e_ref), 1e-2 * float(np.abs(sub.coef).sum()))
+    for dtype in ("c64", "c128"):
+        f32[dtype]["reduced_depth_check"] = dict(
+            layers=2, strings=16, energy=e_gpu[dtype], energy_ref=e_ref,
+            abs_err=abs(e_gpu[dtype] - e_ref), rel_err=abs(e_gpu[dtype] - e_ref) / scale)
+    log(f"[bench] fabric32 reduced depth: E_ref={e_ref:.12f}, |dE| c64 "
+        f"{abs(e_gpu['c64'] - e_ref):.1e}, c128 {abs(e_gpu['c128'] - e_ref):.1e} "
+        f"({time.perf_counter() - t0:.0f} s on the host)")
+    legs["fabric32"] = f32
+    return legs
 
 
 def measure_batch(P, W, torch, args):
@@ -498,6 +652,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-c128", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the hea12 / fabric28 / fabric32 configuration legs")
+    ap.add_argument("--no-fabric32", action="store_true", help="skip the 32-qubit legs")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--tune", action="store_true",
                     help="run the measured tuner on the workload before timing")
@@ -553,6 +710,7 @@ def main():
         res["qsu"]["qr_trend_30q_120_layers"] = qr_trend(P, W)
     c128 = None if (args.no_c128 or res["dtype"] != "c64") else measure_c128(P, W, torch, args)
     grad = None if args.no_grad else measure_grad(P, W, torch, args)
+    legs = None if args.no_legs else measure_legs(P, W, torch, args)
     batch = None if args.no_batch else measure_batch(P, W, torch, args)
     if args.tune_save:
         P.sv_tune_save(args.tune_save)
@@ -581,6 +739,7 @@ def main():
         "c128": c128,
         "grad": grad,
         "batch": batch,
+        "legs": legs,
         "energy": res["energy"],
         "roofline": res["roofline"],
         "cpu_baseline": cpu,

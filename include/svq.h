@@ -101,7 +101,8 @@ typedef struct {
     int32_t n_groups;        /* X/Y flip-mask groups of the Hamiltonian */
     int32_t n_phases;        /* register phases over all passes */
     int32_t tile_k;          /* tile width used (bits) */
-    double bytes;            /* algorithmic HBM bytes of the launched passes */
+    double bytes;            /* algorithmic HBM bytes of the launched passes (sv_grad:
+                                the whole call, forward, H|psi>, dot and reverse) */
     double ms_plan;          /* host planning time, 0 when the plan was cached */
 } svq_stats;
 
@@ -226,6 +227,26 @@ svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *the
                    int n_theta, const svq_pauli *terms, int n_terms, svq_sched sched,
                    double *energy_host, double *energy_dev, double *grad_host,
                    double *grad_dev, svq_stats *stats);
+
+/* Parameter-shift gradient, the comparison method for sv_grad: every
+ * parametric gate j of parameter p is re-evaluated with its angle shifted,
+ * E(+-s) by a full QSU and EVC from psi0 under the given schedule, and
+ * dE/dtheta_p = sum_j scale_j sum_s w_s [E(a_j + s) - E(a_j - s)].
+ * rule SVQ_SHIFT_EXACT: s = pi/2, w = 1/2 for the one-frequency kinds (RX,
+ * RY, RZ, CPHASE); for GIVENS (frequencies 1/2 and 1) the two-frequency rule
+ * s = pi/2, 3pi/2 with w = (sqrt2 + 1)/(4 sqrt2), -(sqrt2 - 1)/(4 sqrt2)
+ * (Wierichs et al., Quantum 6, 677 (2022)).  SVQ_SHIFT_TWO_TERM applies the
+ * one-frequency rule to every gate (two evaluations per gate, exact only for
+ * one-frequency gates).  The combination runs on the device in FP64.
+ * The handle's state is psi0 and is handed back; psi0 is kept in a second
+ * state buffer.  energy_host (nullable) adds one unshifted evaluation;
+ * *n_evals_out (nullable) receives the number of evaluations.  Errors: as
+ * sv_grad, EINVAL for another rule. */
+enum { SVQ_SHIFT_EXACT = 0, SVQ_SHIFT_TWO_TERM = 1 };
+svq_status sv_param_shift_grad(svq_state st, const svq_gate *gates, int m, const double *theta,
+                               int n_theta, const svq_pauli *terms, int n_terms, svq_sched sched,
+                               int rule, double *energy_host, double *grad_host, double *grad_dev,
+                               int *n_evals_out, svq_stats *stats);
 
 /* Host-only planning (no GPU needed), for inspection and tests.
  * Circuit: order_out[m] = gate index at each schedule position,

@@ -52,7 +52,7 @@ class SvqError(RuntimeError):
 EXPORTS = ("sv_create", "sv_destroy", "sv_set_basis", "sv_set_amplitudes", "sv_get_amplitudes",
            "sv_get_layout", "sv_plan_dump", "sv_device_ptr", "sv_apply_circuit",
            "sv_apply_circuit_static", "sv_qr_permute",
-           "sv_expectation", "sv_expectation_qsu", "sv_apply_hamiltonian", "sv_grad", "sv_plan_circuit",
+           "sv_expectation", "sv_expectation_qsu", "sv_apply_hamiltonian", "sv_grad", "sv_param_shift_grad", "sv_plan_circuit",
            "sv_plan_circuit_json", "sv_plan_paulis", "sv_plan_ops", "sv_tune_circuit", "sv_tune_paulis",
            "sv_batch_tune", "sv_tune_save", "sv_tune_load", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
            "sv_batch_destroy", "sv_last_error")
@@ -84,6 +84,10 @@ def _load():
     L.sv_grad.argtypes = [vp, POINTER(svq_gate), c_int, POINTER(c_double), c_int,
                           POINTER(svq_pauli), c_int, c_int, POINTER(c_double), POINTER(c_double),
                           POINTER(c_double), POINTER(c_double), POINTER(svq_stats)]
+    L.sv_param_shift_grad.argtypes = [vp, POINTER(svq_gate), c_int, POINTER(c_double), c_int,
+                                      POINTER(svq_pauli), c_int, c_int, c_int, POINTER(c_double),
+                                      POINTER(c_double), POINTER(c_double), POINTER(c_int),
+                                      POINTER(svq_stats)]
     L.sv_plan_circuit.argtypes = [c_int, c_int, POINTER(svq_gate), c_int, c_int, c_int,
                                   POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                   POINTER(c_uint64), POINTER(c_int32), POINTER(c_int32)]
@@ -288,6 +292,24 @@ def sv_grad(h, gates_c, m, theta, n_theta, terms_c, n_terms, sched, grad_dev=Non
     return e.value, g[:n_theta], st
 
 
+SHIFT_EXACT, SHIFT_TWO_TERM = 0, 1
+
+
+def sv_param_shift_grad(h, gates_c, m, theta, n_theta, terms_c, n_terms, sched, rule=SHIFT_EXACT,
+                        grad_dev=None, want_energy=True):
+    """(E or None, gradient, number of evaluations, stats) by the parameter-shift rules."""
+    st = svq_stats()
+    th = np.ascontiguousarray(theta, dtype=np.float64) if n_theta else np.zeros(1)
+    e = c_double(0.0)
+    g = np.zeros(max(1, n_theta), dtype=np.float64)
+    ne = c_int(0)
+    _check(lib.sv_param_shift_grad(h, gates_c, m, _dptr(th), n_theta, terms_c, n_terms, sched, rule,
+                                   byref(e) if want_energy else None, _dptr(g),
+                                   ctypes.cast(grad_dev, POINTER(c_double)) if grad_dev else None,
+                                   byref(ne), byref(st)))
+    return (e.value if want_energy else None), g[:n_theta], ne.value, st
+
+
 def sv_plan_circuit(n, g, gates, sched, tile_k=0):
     gc = gates_array(gates)
     m = len(gates)
@@ -478,6 +500,11 @@ class State:
         th = circuit.theta if theta is None else theta
         return sv_grad(self.h, gates_array(circuit.gates), len(circuit.gates), th, len(th),
                        paulis_array(ham), len(ham.coef), sched)
+
+    def param_shift_grad(self, circuit, ham, theta=None, sched=LAZY, rule=SHIFT_EXACT):
+        th = circuit.theta if theta is None else theta
+        return sv_param_shift_grad(self.h, gates_array(circuit.gates), len(circuit.gates), th,
+                                   len(th), paulis_array(ham), len(ham.coef), sched, rule)
 
 
 class Batch:

@@ -196,6 +196,7 @@ struct svq_state_s {
         d_energy, d_grad;
     int device = 0;
     // per-launch event timing (sv_profile)
+    double traffic = 0.0;   // algorithmic HBM bytes of every launch so far
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -423,6 +424,7 @@ svq_status run_qr(svq_state st, void *buf, const std::vector<Transposition> &tr)
     QrArgs a = make_qr_args(st->n, st->dbl(), tr);
     ProfScope ps(st, 1);
     HIPCHK(st, launch_qr(st->dbl(), buf, a, st->stream), "qr_permute");
+    st->traffic += qr_bytes(st, tr);
     return SVQ_OK;
 }
 
@@ -549,6 +551,7 @@ svq_status run_circuit_steps(svq_state st, const CircuitPlan &P, const PhaseDesc
                                         ops_dev, nullptr, a.nblocks, st->stream),
                    "gate_pass");
             bytes += 2.0 * (double)st->bytes();
+            st->traffic += 2.0 * (double)st->bytes();
         }
     }
     st->pos = P.pos_after;
@@ -1017,6 +1020,8 @@ svq_status sv_apply_hamiltonian(svq_state st, const svq_pauli *terms, int n_term
                                         (const HpsiGroup *)cp->d_hgroups.p,
                                         (const HpsiTerm *)cp->d_hterms.p, st->stream),
                    "hpsi_pass");
+            // read psi, write lambda (and read it first after the first pass)
+            st->traffic += (any ? 3.0 : 2.0) * (double)st->bytes();
             any = true;
         }
     }
@@ -1025,6 +1030,7 @@ svq_status sv_apply_hamiltonian(svq_state st, const svq_pauli *terms, int n_term
                                       (const WideTerm *)cp->d_wide.p, (int)cp->wide.size(),
                                       any ? 1 : 0, st->stream),
                "hpsi_direct");
+        st->traffic += (any ? 3.0 : 2.0) * (double)st->bytes();
     }
     st->pos = P.pos_after;
     out->pos = P.pos_after;
@@ -1118,6 +1124,7 @@ svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *the
     HIPCHK(st, st->d_grad.ensure(sizeof(double) * std::max(1, n_theta)), "alloc grad");
     double *edev = energy_dev ? energy_dev : (double *)st->d_energy.p;
     double *gdev = grad_dev ? grad_dev : (double *)st->d_grad.p;
+    const double traffic0 = st->traffic;
     // forward
     s = run_circuit(st, cc, gn, theta, stats);
     if (s) return s;
@@ -1136,6 +1143,7 @@ svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *the
     // E = Re <psi|lambda>
     HIPCHK(st, launch_dot_re(st->dbl(), st->buf, st->d_lam.p, st->N(), (double *)st->d_extra.p, st->stream), "dot");
     HIPCHK(st, launch_sum((const double *)st->d_extra.p, dg, edev, st->stream), "sum");
+    st->traffic += 2.0 * (double)st->bytes();
     // back to the circuit's final layout (both states)
     {
         std::vector<int> lp = st->pos;
@@ -1168,6 +1176,7 @@ svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *the
                                             (int)nblocks, st->stream),
                        "adjoint_pass");
             }
+            st->traffic += 4.0 * (double)st->bytes();   // psi and lambda, read and written
             const int g0 = goff[it->idx], gn_pass = goff[it->idx + 1] - g0;
             HIPCHK(st, launch_grad_tiles((const double *)st->d_gpart.p, nblocks, gn_pass,
                                          (const int *)st->d_ggates.p + g0, (double *)st->d_gop.p,
@@ -1183,8 +1192,10 @@ svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *the
                                   (const int *)st->d_pgate.p, n_theta, gdev, st->stream),
            "grad_reduce");
     if (stats) {
+        // every launch of the call: forward, H|psi>, <psi|lambda>, the
+        // relayouts and the reverse sweep (the QRs of both states)
         stats->n_gate_passes += (int)P.passes.size();
-        stats->bytes += (double)P.passes.size() * 4.0 * (double)st->bytes();
+        stats->bytes = st->traffic - traffic0;
         stats->ms_plan += ms;
     }
     if (energy_host)
@@ -1192,6 +1203,146 @@ svq_status sv_grad(svq_state st, const svq_gate *gates, int m, const double *the
     if (grad_host && n_theta)
         HIPCHK(st, hipMemcpyAsync(grad_host, gdev, sizeof(double) * n_theta, hipMemcpyDeviceToHost, st->stream), "D2H");
     // pptr/pgate/ggates host vectors must outlive the async copies
+    HIPCHK(st, hipStreamSynchronize(st->stream), "sync");
+    return SVQ_OK;
+}
+
+svq_status sv_param_shift_grad(svq_state st, const svq_gate *gates, int m, const double *theta,
+                               int n_theta, const svq_pauli *terms, int n_terms, svq_sched sched,
+                               int rule, double *energy_host, double *grad_host, double *grad_dev,
+                               int *n_evals_out, svq_stats *stats) {
+    svq_status s = check_state(st);
+    if (s) return s;
+    if (m < 0 || (m > 0 && !gates) || n_theta < 0) return fail(SVQ_EINVAL, "bad gate list");
+    if (n_terms < 0 || (n_terms > 0 && !terms)) return fail(SVQ_EINVAL, "bad term list");
+    if (sched != SVQ_EAGER && sched != SVQ_LAZY) return fail(SVQ_EINVAL, "bad schedule");
+    if (rule != SVQ_SHIFT_EXACT && rule != SVQ_SHIFT_TWO_TERM) return fail(SVQ_EINVAL, "bad rule");
+    std::vector<GateN> gn;
+    std::string err = normalize_gates(st->n, gates, m, n_theta, gn);
+    if (!err.empty()) return fail(SVQ_EINVAL, err);
+    s = check_theta(gn, theta, n_theta);
+    if (s) return s;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    // Shifted evaluations: (gate, angle shift, coefficient), grouped by
+    // parameter.  One-frequency generators (RX, RY, RZ: spectrum +-1/2;
+    // CPHASE: {0, -1}) take f' = [f(a + pi/2) - f(a - pi/2)] / 2.  GIVENS has
+    // the spectrum {+-1/2, 0, 0}, i.e. the frequencies 1/2 and 1; its exact
+    // rule is the two-frequency equidistant rule with shifts pi/2 and 3pi/2
+    // (Wierichs et al., Quantum 6, 677 (2022)).  The two-term rule applies the
+    // one-frequency rule to every gate (exact only for one frequency).
+    struct Eval { int gate, param; double shift, coef; };
+    std::vector<std::vector<Eval>> byp(n_theta);
+    const double r2 = std::sqrt(2.0), pi = 3.14159265358979323846;
+    const double ga = (r2 + 1.0) / (4.0 * r2), gb = (r2 - 1.0) / (4.0 * r2);
+    for (int j = 0; j < m; ++j) {
+        const GateN &g = gn[j];
+        if (g.param < 0) continue;
+        std::vector<std::pair<double, double>> rl;
+        if (g.kind == SVQ_GIVENS && rule == SVQ_SHIFT_EXACT)
+            rl = {{pi / 2, ga}, {3 * pi / 2, -gb}};
+        else
+            rl = {{pi / 2, 0.5}};
+        for (const auto &r : rl) {
+            byp[g.param].push_back({j, g.param, +r.first, +r.second * g.scale});
+            byp[g.param].push_back({j, g.param, -r.first, -r.second * g.scale});
+        }
+    }
+    std::vector<Eval> ev;
+    std::vector<int> ptr(n_theta + 1, 0);
+    std::vector<double> coef;
+    for (int p = 0; p < n_theta; ++p) {
+        for (const Eval &e : byp[p]) {
+            ev.push_back(e);
+            coef.push_back(e.coef);
+        }
+        ptr[p + 1] = (int)ev.size();
+    }
+    const int ne = (int)ev.size();
+    if (n_evals_out) *n_evals_out = ne + (energy_host ? 1 : 0);
+    // plans and scratch before the first launch
+    const int k = default_k(st);
+    const std::vector<int> pos0 = st->pos;
+    CachedCircuit *cc = nullptr;
+    double ms = 0;
+    s = get_circuit_plan(st, gn, sched, k, false, &cc, &ms);
+    if (s) return s;
+    CachedPaulis *cp = nullptr;
+    {
+        const std::vector<int> keep = st->pos;
+        st->pos = cc->plan.pos_after;
+        double msp = 0;
+        s = get_pauli_plan(st, terms, n_terms, sched, &cp, &msp);
+        st->pos = keep;
+        if (s) return s;
+    }
+    HIPCHK(st, st->d_lam.ensure(st->bytes()), "alloc psi0 copy");
+    HIPCHK(st, st->d_gop.ensure(sizeof(double) * (size_t)std::max(1, ne + 1)), "alloc energies");
+    HIPCHK(st, st->d_gpart.ensure(sizeof(double) * (size_t)std::max(1, ne)), "alloc coefficients");
+    HIPCHK(st, st->d_pptr.ensure(sizeof(int) * ptr.size()), "alloc ptr");
+    HIPCHK(st, st->d_grad.ensure(sizeof(double) * std::max(1, n_theta)), "alloc grad");
+    HIPCHK(st, st->d_ops.ensure(sizeof(OpDesc) * std::max<size_t>(1, cc->plan.ops.size())), "alloc ops");
+    {
+        const int nchunk = 1 << st->g;
+        HIPCHK(st, st->d_partials.ensure(sizeof(double) * std::max(1, cp->plan.total_blocks)), "alloc partials");
+        HIPCHK(st, st->d_chunks.ensure(sizeof(double) * (nchunk + reduce_scratch(nchunk))), "alloc chunks");
+        HIPCHK(st, st->d_extra.ensure(sizeof(double) * direct_grid(st->N())), "alloc extra");
+    }
+    double *evals = (double *)st->d_gop.p;
+    double *gdev = grad_dev ? grad_dev : (double *)st->d_grad.p;
+    const double traffic0 = st->traffic;
+    // psi0 is kept aside and restored before every evaluation
+    HIPCHK(st, hipMemcpyAsync(st->d_lam.p, st->buf, st->bytes(), hipMemcpyDeviceToDevice, st->stream),
+           "save psi0");
+    st->traffic += 2.0 * (double)st->bytes();
+    std::vector<GateN> gs = gn;
+    svq_stats one;
+    for (int e = 0; e <= ne; ++e) {
+        if (e == ne && !energy_host) break;
+        if (e > 0) {
+            HIPCHK(st, hipMemcpyAsync(st->buf, st->d_lam.p, st->bytes(), hipMemcpyDeviceToDevice,
+                                      st->stream),
+                   "restore psi0");
+            st->traffic += 2.0 * (double)st->bytes();
+            st->pos = pos0;
+        }
+        // angle shift of one gate (the plan does not depend on angles)
+        if (e < ne) gs[ev[e].gate].offset = gn[ev[e].gate].offset + ev[e].shift;
+        std::memset(&one, 0, sizeof(one));
+        s = run_circuit(st, cc, gs, theta, &one);
+        if (s) return s;
+        if (e < ne) gs[ev[e].gate].offset = gn[ev[e].gate].offset;
+        s = run_expectation(st, cp, evals + e, nullptr, &one);
+        if (s) return s;
+        st->traffic += (double)one.n_evc_passes * (double)st->bytes();
+        if (stats) {
+            stats->n_qr += one.n_qr;
+            stats->n_gate_passes += one.n_gate_passes;
+            stats->n_evc_passes += one.n_evc_passes;
+        }
+    }
+    HIPCHK(st, hipMemcpyAsync(st->d_gpart.p, coef.data(), sizeof(double) * std::max(1, ne),
+                              hipMemcpyHostToDevice, st->stream),
+           "upload coefficients");
+    HIPCHK(st, hipMemcpyAsync(st->d_pptr.p, ptr.data(), sizeof(int) * ptr.size(),
+                              hipMemcpyHostToDevice, st->stream),
+           "upload ptr");
+    HIPCHK(st, launch_shift_combine(evals, (const double *)st->d_gpart.p, (const int *)st->d_pptr.p,
+                                    n_theta, gdev, st->stream),
+           "shift_combine");
+    // hand psi0 back, as sv_grad does
+    HIPCHK(st, hipMemcpyAsync(st->buf, st->d_lam.p, st->bytes(), hipMemcpyDeviceToDevice, st->stream),
+           "restore psi0");
+    st->traffic += 2.0 * (double)st->bytes();
+    st->pos = pos0;
+    if (stats) {
+        stats->bytes = st->traffic - traffic0;
+        stats->ms_plan = ms;
+        stats->tile_k = cc->plan.k;
+    }
+    if (energy_host)
+        HIPCHK(st, hipMemcpyAsync(energy_host, evals + ne, sizeof(double), hipMemcpyDeviceToHost, st->stream), "D2H");
+    if (grad_host && n_theta)
+        HIPCHK(st, hipMemcpyAsync(grad_host, gdev, sizeof(double) * n_theta, hipMemcpyDeviceToHost, st->stream), "D2H");
     HIPCHK(st, hipStreamSynchronize(st->stream), "sync");
     return SVQ_OK;
 }

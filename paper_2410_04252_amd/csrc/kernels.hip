@@ -1409,6 +1409,26 @@ hipError_t launch_grad_reduce(const double *gpart, int nper, const int *pptr, co
     return hipGetLastError();
 }
 
+// grad[p] = sum over e in [ptr[p], ptr[p+1]) of coef[e] * evals[e] (fixed order).
+__global__ __launch_bounds__(64) void k_shift_combine(const double *__restrict__ evals,
+                                                       const double *__restrict__ coef,
+                                                       const int *__restrict__ ptr, int nparam,
+                                                       double *__restrict__ grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nparam) return;
+    double acc = 0.0;
+    for (int e = ptr[p]; e < ptr[p + 1]; ++e) acc += coef[e] * evals[e];
+    grad[p] = acc;
+}
+
+hipError_t launch_shift_combine(const double *evals, const double *coef, const int *ptr, int nparam,
+                                double *grad, hipStream_t s) {
+    if (nparam == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_shift_combine, dim3((nparam + 63) / 64), dim3(64), 0, s, evals, coef, ptr,
+                       nparam, grad);
+    return hipGetLastError();
+}
+
 hipError_t launch_grad_tiles(const double *gpart, uint32_t ntiles, int nslots, const int *gates,
                              double *gop, hipStream_t s) {
     if (nslots == 0) return hipSuccess;

@@ -61,6 +61,10 @@ hipError_t launch_grad_reduce(const double *gpart, int nper, const int *pptr, co
 // block partials of one adjoint pass).
 hipError_t launch_grad_tiles(const double *gpart, uint32_t ntiles, int nslots, const int *gates,
                              double *gop, hipStream_t s);
+// grad[p] = sum_{e in [ptr[p], ptr[p+1])} coef[e] * evals[e]: the
+// parameter-shift combination of shifted energies.
+hipError_t launch_shift_combine(const double *evals, const double *coef, const int *ptr, int nparam,
+                                double *grad, hipStream_t s);
 hipError_t launch_fill_basis(bool dbl, void *psi, uint64_t N, uint64_t idx, hipStream_t s);
 // Reset counters (fill kernel) and launch the persistent batch kernel.
 hipError_t launch_batch(const BatchArgs &a, int32_t *counters, int ncounters, hipStream_t s,
