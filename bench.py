@@ -31,6 +31,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gate_pass_fabric30.json")
 TRAFFIC_FILE_C128 = os.path.join(ROOT, "profiles", "traffic_gate_pass_fabric30_c128.json")
 
 
+ELEM = {"c64": "float", "c128": "double"}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -41,6 +44,21 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, "paper_2410_04252_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def counted_traffic(path, kernel, workload):
+    """Per-launch HBM bytes of the gate pass from the committed counter
+    summary, or None when it was taken on another workload, another kernel
+    instance or older kernel sources."""
+    if workload != "fabric30" or not os.path.exists(path):
+        return None
+    try:
+        tf = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if tf.get("source_hash") != kernel_source_hash() or kernel not in tf.get("instances", []):
+        return None
+    return tf.get("bytes_per_launch")
 
 
 def measure_main(P, W, torch, args):
@@ -124,7 +142,7 @@ def measure_main(P, W, torch, args):
                      plan_ms=s2.ms_plan, roofline=evc_roof),
             roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                          kernel="k_gate_pass<float,%d,4,false,true>" % (s1.tile_k or 12),
+                          kernel="k_gate_pass<%s,%d,4,false,true>" % (ELEM[dtype], s1.tile_k or 12),
                           bytes_per_launch=gp_bytes, launches=n_gp, avg_ms=gp_avg_ms))
     # eager comparison (one run, not part of the timed steps)
     P.sv_set_basis(h, circ.psi0_index)
@@ -171,7 +189,7 @@ def measure_main(P, W, torch, args):
         qsu_evc=qsu_evc, tuned=tuned,
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                      kernel="k_gate_pass<float,%d,4,false,true>" % (s1.tile_k or 12),
+                      kernel="k_gate_pass<%s,%d,4,false,true>" % (ELEM[dtype], s1.tile_k or 12),
                       bytes_per_launch=gp_bytes, launches=n_gp, avg_ms=gp_avg_ms),
     )
     return out
@@ -196,24 +214,25 @@ def evc_roofline(n, nt, evc_pass_ms_per_step, dtype):
                 flops_per_step=flops, pass_ms_per_step=evc_pass_ms_per_step)
 
 
-def measure_copy_gbs(torch):
-    """Achievable device bandwidth: a plain 8 GiB -> 8 GiB torch copy (bytes
-    read + written over the kernel time, best of three)."""
-    a = torch.empty(1 << 30, dtype=torch.complex64, device="cuda")
+def measure_copy_gbs(P, torch, nbytes=8 << 30):
+    """Achievable device bandwidth: the library's plain streaming copy of
+    8 GiB (bytes read + written over the kernel time, best of three)."""
+    a = torch.empty(nbytes // 8, dtype=torch.complex64, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1.0)
-    b.copy_(a)
+    stream = torch.cuda.current_stream()
+    P.sv_device_copy(a.data_ptr(), b.data_ptr(), nbytes, stream)
     best = 1e30
     for _ in range(3):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        b.copy_(a)
-        e1.record()
+        e0.record(stream)
+        P.sv_device_copy(a.data_ptr(), b.data_ptr(), nbytes, stream)
+        e1.record(stream)
         e1.synchronize()
         best = min(best, e0.elapsed_time(e1))
     del a, b
     torch.cuda.empty_cache()
-    return 2.0 * (1 << 30) * 8 / (best * 1e-3) / 1e9
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
 
 
 def qr_trend(P, W):
@@ -288,14 +307,8 @@ def measure_c128(P, W, torch, args):
     gbs = 2 * S / (gp_avg * 1e-3) / 1e9
     log(f"[bench] c128: gate pass {gp_avg:.2f} ms ({gbs:.0f} GB/s), "
         f"{s1.n_gate_passes} passes; EVC passes {t_ev / reps:.1f} ms; E={e:.12f}")
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE_C128):
-        try:
-            tf = json.load(open(TRAFFIC_FILE_C128))
-            if tf.get("source_hash") == kernel_source_hash():
-                traffic = tf.get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    kname = "k_gate_pass<double,%d,4,false,true>" % (s1.tile_k or 12)
+    traffic = counted_traffic(TRAFFIC_FILE_C128, kname, args.workload)
     return dict(workload=args.workload, dtype="c128", gate_passes=s1.n_gate_passes, tile_k=s1.tile_k,
                 qr_lazy=s1.n_qr, gate_pass_avg_ms=gp_avg, qr_pass_avg_ms=qr_avg,
                 qsu_ms_kernels=qsu_ms, qsu_gates_per_s_kernels=m / (qsu_ms * 1e-3),
@@ -303,8 +316,7 @@ def measure_c128(P, W, torch, args):
                 energy=e,
                 roofline=dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                               frac=round(gbs / HBM_PEAK_GBS, 4), traffic=traffic,
-                              kernel="k_gate_pass<double,%d,4,false,true>" % (s1.tile_k or 12),
-                              bytes_per_launch=2 * S, launches=n_gp, avg_ms=gp_avg),
+                              kernel=kname, bytes_per_launch=2 * S, launches=n_gp, avg_ms=gp_avg),
                 evc_roofline=evc_roofline(n, nt, t_ev / reps, "c128"))
 
 
@@ -365,7 +377,7 @@ def measure_grad(P, W, torch, args):
                 adjoint_gbs=sg.bytes / (adj_ms * 1e-3) / 1e9,
                 adjoint_roofline=dict(bound="hbm", achieved=round(adj_gbs, 1), peak=HBM_PEAK_GBS,
                                       unit="GB/s", frac=round(adj_gbs / HBM_PEAK_GBS, 4),
-                                      kernel="k_gate_pass<float,k,4,true,true>",
+                                      kernel="k_gate_pass<float,%d,4,true,true>" % sg.tile_k,
                                       bytes_per_launch=4 * S, launches=n_adj, avg_ms=adj_avg),
                 param_shift_ms=ps_ms, param_shift_grad_per_s=1e3 / ps_ms,
                 param_shift_evaluations=nev_exact,
@@ -463,10 +475,19 @@ def measure_legs(P, W, torch, args):
             f"{L['qr_lazy']} vs eager {L['qr_eager']}), gate pass {L['gate_pass_gbs']:.0f} GB/s; "
             f"EVC {L['evc_ms']:.0f} ms ({L['terms_per_s']:.0f} terms/s, QR {L['evc_qr_lazy']} vs "
             f"{L['evc_qr_eager']})")
-    # reduced depth against the oracle (2 layers of the same seeded ansatz)
+    # reduced depth against the oracle (2 layers of the same seeded ansatz).
+    # Two layers move the 10 electrons of psi0 only near the boundary of the
+    # occupied orbitals, so the check uses strings whose sites all lie there
+    # (qubits 4..15), 8 diagonal and 8 with X/Y sites, drawn from the 10^4.
     short = W.fabric(32, 2, W.SEED_BASE + 3)
     rng = np.random.default_rng(3232)
-    pick = np.sort(rng.choice(len(ham.coef), size=16, replace=False))
+    band = ((1 << 16) - 1) & ~((1 << 4) - 1)
+    inside = [i for i in range(len(ham.coef))
+              if (int(ham.x[i]) | int(ham.z[i])) & ~band == 0]
+    diag = [i for i in inside if int(ham.x[i]) == 0]
+    offd = [i for i in inside if int(ham.x[i]) != 0]
+    pick = np.sort(np.concatenate([rng.choice(diag, size=min(8, len(diag)), replace=False),
+                                   rng.choice(offd, size=min(8, len(offd)), replace=False)]))
     sub = W.Hamiltonian(32, ham.x[pick], ham.z[pick], ham.coef[pick])
     e_gpu = {}
     for dtype in ("c64", "c128"):
@@ -485,7 +506,7 @@ def measure_legs(P, W, torch, args):
     scale = max(abs(e_ref), 1e-2 * float(np.abs(sub.coef).sum()))
     for dtype in ("c64", "c128"):
         f32[dtype]["reduced_depth_check"] = dict(
-            layers=2, strings=16, energy=e_gpu[dtype], energy_ref=e_ref,
+            layers=2, strings=len(pick), energy=e_gpu[dtype], energy_ref=e_ref,
             abs_err=abs(e_gpu[dtype] - e_ref), rel_err=abs(e_gpu[dtype] - e_ref) / scale)
     log(f"[bench] fabric32 reduced depth: E_ref={e_ref:.12f}, |dE| c64 "
         f"{abs(e_gpu['c64'] - e_ref):.1e}, c128 {abs(e_gpu['c128'] - e_ref):.1e} "
@@ -615,27 +636,46 @@ def _pmc_rows(d, counter):
     return rows
 
 
-def ingest_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, tile_k=0):
-    """FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by the
-    bytes a plain device copy of known size really moves per KiB counted."""
-    def avg(rows, pat):
-        v = [x for k, x in rows if pat in k]
-        return sum(v) / len(v) if v else None, len(v)
-    gf, nf = avg(_pmc_rows(fetch_dir, "FETCH_SIZE"), "k_gate_pass")
-    gw, nw = avg(_pmc_rows(write_dir, "WRITE_SIZE"), "k_gate_pass")
-    cf, _ = avg(_pmc_rows(copy_fetch_dir, "FETCH_SIZE"), "")
-    cw, _ = avg(_pmc_rows(copy_write_dir, "WRITE_SIZE"), "")
-    copy_bytes = (1 << 27) * 8
-    f_fetch = copy_bytes / (cf * 1024.0)
-    f_write = copy_bytes / (cw * 1024.0)
-    traffic = gf * 1024.0 * f_fetch + gw * 1024.0 * f_write
-    out = dict(kernel="k_gate_pass (fabric30, lazy)", source_hash=kernel_source_hash(),
-               fetch_kib_per_launch=gf, write_kib_per_launch=gw, launches=[nf, nw],
-               copy_fetch_kib=cf, copy_write_kib=cw, copy_bytes=copy_bytes,
-               scale_fetch=f_fetch, scale_write=f_write, bytes_per_launch=traffic,
-               algorithmic_bytes_per_launch=2 * (1 << 30) * 8)
-    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
-    with open(TRAFFIC_FILE, "w") as fh:
+def _avg(rows, pat):
+    v = [x for k, x in rows if pat in k]
+    return (sum(v) / len(v) if v else None), len(v)
+
+
+def hbm_bytes(rd_dir, wr_dir, pat):
+    """HBM bytes per dispatch of the kernels whose name contains pat, from the
+    L2-to-fabric request counters summed over all 16 channels of all 8 XCDs:
+    a read request moves a 128-byte line (32 bytes when flagged 32B), a write
+    request 64 bytes (32 when not flagged 64B).  Runs: rd_dir with
+    TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum, wr_dir with TCC_EA0_WRREQ_sum
+    TCC_EA0_WRREQ_64B_sum."""
+    rq, n1 = _avg(_pmc_rows(rd_dir, "TCC_EA0_RDREQ_sum"), pat)
+    r32, _ = _avg(_pmc_rows(rd_dir, "TCC_EA0_RDREQ_32B_sum"), pat)
+    wq, n2 = _avg(_pmc_rows(wr_dir, "TCC_EA0_WRREQ_sum"), pat)
+    w64, _ = _avg(_pmc_rows(wr_dir, "TCC_EA0_WRREQ_64B_sum"), pat)
+    rd = 128.0 * (rq - r32) + 32.0 * r32
+    wr = 64.0 * w64 + 32.0 * (wq - w64)
+    return rd, wr, (n1, n2)
+
+
+def ingest_pmc(rd_dir, wr_dir, copy_rd_dir, copy_wr_dir, dtype="c64", tile_k=0):
+    """Per-launch HBM traffic of the gate pass from the request counters,
+    checked on a plain copy of known size (1 GiB read, 1 GiB written per
+    launch), which must read 1.0 of its bytes."""
+    rd, wr, n = hbm_bytes(rd_dir, wr_dir, "k_gate_pass")
+    crd, cwr, _ = hbm_bytes(copy_rd_dir, copy_wr_dir, "k_copy")
+    names = sorted({k.split("(")[0].replace("void svq::", "").replace(" ", "")
+                    for k, _ in _pmc_rows(rd_dir, "TCC_EA0_RDREQ_sum") if "k_gate_pass" in k})
+    S = (1 << 30) * (8 if dtype == "c64" else 16)
+    out = dict(kernel="k_gate_pass (fabric30, lazy, %s)" % dtype, source_hash=kernel_source_hash(),
+               method="TCC_EA0_RDREQ_sum x 128 B (32 B requests x 32), TCC_EA0_WRREQ_64B_sum x 64 B "
+                      "(others x 32), summed over 16 channels x 8 XCDs",
+               instances=names, read_bytes_per_launch=rd, write_bytes_per_launch=wr, launches=list(n),
+               copy_read_ratio=crd / float(1 << 30), copy_write_ratio=cwr / float(1 << 30),
+               bytes_per_launch=rd + wr, algorithmic_bytes_per_launch=2 * S,
+               ratio_to_algorithmic=(rd + wr) / (2 * S))
+    path = TRAFFIC_FILE if dtype == "c64" else TRAFFIC_FILE_C128
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
 
@@ -663,50 +703,42 @@ def main():
                     help="skip the eager-schedule and QSU-based comparisons (profiling runs)")
     ap.add_argument("--qsu-terms", type=int, default=64,
                     help="Pauli strings timed with the QSU-based comparison method (0: skip)")
-    ap.add_argument("--copy-calib", action="store_true",
-                    help="run only a plain 1 GiB device copy (traffic-counter calibration)")
-    ap.add_argument("--ingest-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
-                                                       "COPY_WRITE_DIR"),
-                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this benchmark and "
-                         "of --copy-calib into the per-launch HBM traffic of the gate pass")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only three plain 1 GiB device copies (traffic-counter calibration)")
+    ap.add_argument("--ingest-pmc", nargs=4, metavar=("RD_DIR", "WR_DIR", "COPY_RD_DIR",
+                                                       "COPY_WR_DIR"),
+                    help="turn rocprofv3 --pmc request-counter runs of this benchmark and of "
+                         "--copy-probe into the per-launch HBM traffic of the gate pass")
     args = ap.parse_args()
     if args.ingest_pmc:
-        ingest_pmc(*args.ingest_pmc, tile_k=args.tile_k)
+        ingest_pmc(*args.ingest_pmc, dtype=args.dtype or "c64", tile_k=args.tile_k)
         return
     if args.gpus != 1:
         print("bench.py: measures one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
-    if args.copy_calib:
-        a = torch.empty(1 << 27, dtype=torch.complex64, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8,
-                          "launches": 3}))
-        return
     import paper_2410_04252_amd as P
     import workloads as W
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        a = torch.zeros((1 << 30) // 8, dtype=torch.complex64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            P.sv_device_copy(a.data_ptr(), b.data_ptr(), 1 << 30, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "launches": 3}))
+        return
     res = measure_main(P, W, torch, args)
     res["workload"] = args.workload
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            tf = json.load(open(TRAFFIC_FILE))
-            if tf.get("source_hash") == kernel_source_hash():
-                traffic = tf.get("bytes_per_launch")
-        except Exception:
-            traffic = None
-    res["roofline"]["traffic"] = traffic
+    res["roofline"]["traffic"] = counted_traffic(
+        TRAFFIC_FILE if res["dtype"] == "c64" else TRAFFIC_FILE_C128,
+        res["roofline"]["kernel"], args.workload)
     if not args.no_eager:
-        copy_gbs = measure_copy_gbs(torch)
+        copy_gbs = measure_copy_gbs(P, torch)
         res["roofline"]["copy_gbs"] = round(copy_gbs, 1)
-        res["roofline"]["frac_of_torch_copy"] = round(res["roofline"]["achieved"] / copy_gbs, 4)
+        res["roofline"]["frac_of_copy"] = round(res["roofline"]["achieved"] / copy_gbs, 4)
         log(f"[bench] plain device copy {copy_gbs:.0f} GB/s; gate pass at "
-            f"{res['roofline']['frac_of_torch_copy'] * 100:.1f}% of it")
+            f"{res['roofline']['frac_of_copy'] * 100:.1f}% of it")
         res["qsu"]["qr_trend_30q_120_layers"] = qr_trend(P, W)
     c128 = None if (args.no_c128 or res["dtype"] != "c64") else measure_c128(P, W, torch, args)
     grad = None if args.no_grad else measure_grad(P, W, torch, args)

@@ -349,6 +349,12 @@ svq_status sv_plan_ops(int n, int n_local, const uint64_t *targets, int m, int m
                        int n_intra, int fill_highest, int32_t *order_out, uint64_t *local_out,
                        uint64_t *intra_out, int32_t *n_qr_out, int32_t *n_inter_out);
 
+/* A plain streaming copy of device memory (16-byte accesses, asynchronous on
+ * the stream): the reference against which pass bandwidths and the HBM
+ * traffic counters are calibrated.  bytes must be a multiple of 16; the
+ * ranges must not overlap.  Errors: EINVAL, EHIP. */
+svq_status sv_device_copy(const void *src, void *dst, size_t bytes, void *stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *sv_last_error(void);
 

@@ -55,7 +55,7 @@ EXPORTS = ("sv_create", "sv_destroy", "sv_set_basis", "sv_set_amplitudes", "sv_g
            "sv_expectation", "sv_expectation_qsu", "sv_apply_hamiltonian", "sv_grad", "sv_param_shift_grad", "sv_plan_circuit",
            "sv_plan_circuit_json", "sv_plan_paulis", "sv_plan_ops", "sv_tune_circuit", "sv_tune_paulis",
            "sv_batch_tune", "sv_tune_save", "sv_tune_load", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
-           "sv_batch_destroy", "sv_last_error")
+           "sv_batch_destroy", "sv_device_copy", "sv_last_error")
 
 
 def _load():
@@ -117,6 +117,7 @@ def _load():
                               POINTER(c_int32), POINTER(c_int32)]
     L.sv_profile.argtypes = [vp, c_int]
     L.sv_profile_read.argtypes = [vp, c_int, POINTER(c_int), POINTER(c_double)]
+    L.sv_device_copy.argtypes = [vp, vp, c_size_t, vp]
     L.sv_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "sv_last_error":
@@ -224,6 +225,10 @@ def sv_plan_dump(h):
     buf = ctypes.create_string_buffer(need.value)
     _check(lib.sv_plan_dump(h, buf, need.value, None))
     return json.loads(buf.value.decode())
+
+
+def sv_device_copy(src_ptr, dst_ptr, nbytes, stream=None):
+    _check(lib.sv_device_copy(c_void_p(src_ptr), c_void_p(dst_ptr), nbytes, _stream_ptr(stream)))
 
 
 def sv_device_ptr(h):

@@ -844,6 +844,14 @@ svq_status sv_get_amplitudes(svq_state st, void *host) {
     return SVQ_OK;
 }
 
+svq_status sv_device_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    if (!src || !dst) return fail(SVQ_EINVAL, "null pointer");
+    if (bytes % 16) return fail(SVQ_EINVAL, "bytes must be a multiple of 16");
+    hipError_t e = launch_copy(src, dst, bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SVQ_EHIP, std::string("copy: ") + hipGetErrorString(e));
+    return SVQ_OK;
+}
+
 svq_status sv_plan_dump(svq_state st, char *json_buf, size_t cap, size_t *len_out) {
     if (!st) return fail(SVQ_EINVAL, "null handle");
     const std::string empty = "{}";

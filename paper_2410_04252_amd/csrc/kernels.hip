@@ -1409,6 +1409,24 @@ hipError_t launch_grad_reduce(const double *gpart, int nper, const int *pptr, co
     return hipGetLastError();
 }
 
+// Plain streaming copy (16-byte accesses): the reference for achievable
+// bandwidth and for calibrating the HBM traffic counters.
+__global__ __launch_bounds__(256) void k_copy(const float4 *__restrict__ a, float4 *__restrict__ b,
+                                              uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s) {
+    const uint64_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    const uint64_t want = (n + 255) / 256;
+    const uint32_t grid = (uint32_t)(want < 8192 ? want : 8192);
+    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, s, (const float4 *)src, (float4 *)dst, n);
+    return hipGetLastError();
+}
+
 // grad[p] = sum over e in [ptr[p], ptr[p+1]) of coef[e] * evals[e] (fixed order).
 __global__ __launch_bounds__(64) void k_shift_combine(const double *__restrict__ evals,
                                                        const double *__restrict__ coef,

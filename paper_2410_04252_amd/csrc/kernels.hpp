@@ -65,6 +65,8 @@ hipError_t launch_grad_tiles(const double *gpart, uint32_t ntiles, int nslots, c
 // parameter-shift combination of shifted energies.
 hipError_t launch_shift_combine(const double *evals, const double *coef, const int *ptr, int nparam,
                                 double *grad, hipStream_t s);
+// dst[0, bytes) = src[0, bytes), bytes a multiple of 16.
+hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_fill_basis(bool dbl, void *psi, uint64_t N, uint64_t idx, hipStream_t s);
 // Reset counters (fill kernel) and launch the persistent batch kernel.
 hipError_t launch_batch(const BatchArgs &a, int32_t *counters, int ncounters, hipStream_t s,
