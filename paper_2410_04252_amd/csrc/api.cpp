@@ -125,8 +125,20 @@ std::string circuit_json(const CircuitPlan &P, svq_sched sched, bool adj) {
         json_bits(o, a.tphys, P.k);
         o += ",\"tile_bits_out\":";
         json_bits(o, a.tphys_out, P.k);
+        o += ",\"swz\":";
+        json_bits(o, a.swz, P.k);
         o += ",\"gates\":" + std::to_string(gates_in_pass[s.idx]);
-        o += ",\"phases\":" + std::to_string(a.nphase) + "}";
+        o += ",\"phases\":" + std::to_string(a.nphase) + ",\"lanes\":[";
+        for (int ph = 0; ph < a.nphase; ++ph) {
+            if (ph) o += ",";
+            json_bits(o, P.phases[a.phase0 + ph].lane, 6);
+        }
+        o += "],\"regs\":[";
+        for (int ph = 0; ph < a.nphase; ++ph) {
+            if (ph) o += ",";
+            json_bits(o, P.phases[a.phase0 + ph].reg, P.rb);
+        }
+        o += "]}";
     }
     o += "],\"pos_before\":[";
     for (size_t q = 0; q < P.pos_before.size(); ++q) o += (q ? "," : "") + std::to_string(P.pos_before[q]);
@@ -1606,7 +1618,10 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
         for (const PassArgs &pa : cp.passes) {
             BatchPass bp;
             std::memset(&bp, 0, sizeof(bp));
-            for (int j = 0; j < 16; ++j) bp.tphys[j] = pa.tphys[j];
+            for (int j = 0; j < 16; ++j) {
+                bp.tphys[j] = pa.tphys[j];
+                bp.swz[j] = pa.swz[j];
+            }
             bp.phase0 = pa.phase0 + ph_base;
             bp.nphase = pa.nphase;
             passes.push_back(bp);

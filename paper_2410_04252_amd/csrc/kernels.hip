@@ -26,13 +26,6 @@ __device__ __forceinline__ uint64_t spread(uint64_t b, const TI *pos, int k) {
     return b;
 }
 
-// LDS slot of tile-local index t: the six low bits are XORed with the folded
-// higher bits so that a wave whose lanes walk any six tile bits with distinct
-// residues mod 6 hits 64 distinct 8-byte slots modulo 64.
-__device__ __forceinline__ uint32_t swz(uint32_t t) {
-    return t ^ (((t >> 6) ^ (t >> 12)) & 63u);
-}
-
 // ---------------------------------------------------------------------------
 // register-tile gate kernels
 // ---------------------------------------------------------------------------
@@ -380,8 +373,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ---- the pass ---------------------------------------------------------------
 
 // The maps register index j -> physical offset and j -> LDS slot are linear
-// over GF(2) (sums of disjoint bits; the swizzle is an XOR map), so they are
-// built from RB basis values instead of bit by bit.
+// over GF(2) (sums of disjoint bits; the pass's slot map is an XOR map), so
+// they are built from RB basis values instead of bit by bit.
 template <int RB, int K>
 struct RegMap {
     uint32_t ph[RB];    // physical offset of register bit b
@@ -390,9 +383,8 @@ struct RegMap {
     __device__ __forceinline__ void init(const PhaseDesc &P, const TI *tphys) {
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
-            const int t = P.reg[b];
-            ph[b] = 1u << tphys[t];
-            sl[b] = swz(1u << t);
+            ph[b] = 1u << tphys[P.reg[b]];
+            sl[b] = (uint32_t)P.rsl[b];
         }
     }
     __device__ __forceinline__ uint32_t phys(int j) const {
@@ -419,17 +411,17 @@ __device__ __forceinline__ void thread_maps(const PhaseDesc &P, const TI *tphys,
 #pragma unroll
     for (int b = 0; b < 6; ++b) {
         const uint32_t bit = (lane >> b) & 1u;
-        t |= bit << P.lane[b];
+        t ^= bit ? (uint32_t)P.lsl[b] : 0u;
         p |= bit << tphys[P.lane[b]];
     }
 #pragma unroll
     for (int b = 0; b < NWB; ++b) {
         const uint32_t bit = (wave >> b) & 1u;
-        t |= bit << P.wave[b];
+        t ^= bit ? (uint32_t)P.wsl[b] : 0u;
         p |= bit << tphys[P.wave[b]];
     }
     tp = p;
-    tslot = swz(t);
+    tslot = t;
 }
 
 // Tile loads and stores.  With OFF32 the in-tile byte offset fits 32 bits

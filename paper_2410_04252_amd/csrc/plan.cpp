@@ -855,6 +855,171 @@ static void plan_phases(int k, int rb, const std::vector<L3Gate> &gs, CircuitPla
     P.n_phases_total += (int)phs.size();
 }
 
+// ---- LDS slot map of a gate pass ------------------------------------------
+// A transpose between two phases writes the tile to LDS with one phase's
+// (lane, wave, register) mapping and reads it back with the next phase's.
+// Tile index t lives in slot f(t) = XOR of swz[j] over the set bits j of t;
+// f is a bijection of the tile when swz[0..5] are linearly independent six-bit
+// values and swz[j] = 2^j ^ (a six-bit value) for j >= 6.
+//
+// gfx950's LDS serves the 8-byte accesses of a wave in groups of 16 and of 32
+// lanes and its 16-byte accesses in groups of 8 lanes; a group runs without
+// bank conflicts when its slots are distinct modulo 16, 32 and 8 respectively
+// (measured with SQ_LDS_BANK_CONFLICT on single-pattern kernels).  Lane bit b
+// adds swz[lane[b]] to the slot, so a phase is conflict-free when the swz
+// values of its first three, four and five lanes are linearly independent
+// modulo 8, 16 and 32.  The lanes of a phase may be listed in any order, but
+// the load and store phases keep the tile bits on the lowest physical
+// positions as their first lanes (coalescing).  The planner searches swz
+// values, and a lane order per phase, under which every phase of the pass
+// meets the condition.
+
+static int gf2_rank(const uint32_t *v, int n, uint32_t mask) {
+    uint32_t piv[32] = {0};
+    int r = 0;
+    for (int i = 0; i < n; ++i) {
+        uint32_t x = v[i] & mask;
+        while (x) {
+            const int hb = 31 - __builtin_clz(x);
+            if (!piv[hb]) {
+                piv[hb] = x;
+                ++r;
+                break;
+            }
+            x ^= piv[hb];
+        }
+    }
+    return r;
+}
+
+// An order of the six lane bits L (tile-local) whose first 3/4/5 entries meet
+// the bank condition under sv, with the nr required bits req first; false if
+// there is none.
+static bool lane_chain(const int32_t *L, const int *req, int nr, const uint32_t *sv, int32_t *order) {
+    uint32_t rmask = 0;
+    for (int i = 0; i < nr; ++i) rmask |= 1u << req[i];
+    auto fits = [&](uint32_t S, int p) {
+        // the first p lanes are S: S inside the required set while it lasts,
+        // and holding all of it after that
+        return nr >= p ? (S & ~rmask) == 0 : (rmask & ~S) == 0;
+    };
+    auto vals = [&](uint32_t S, uint32_t *v) {
+        int c = 0;
+        for (int i = 0; i < 6; ++i)
+            if ((S >> L[i]) & 1) v[c++] = sv[L[i]];
+        return c;
+    };
+    uint32_t all = 0;
+    for (int i = 0; i < 6; ++i) all |= 1u << L[i];
+    uint32_t v[6];
+    for (int ix = 0; ix < 6; ++ix) {
+        const uint32_t S5 = all & ~(1u << L[ix]);
+        if (!fits(S5, 5) || gf2_rank(v, vals(S5, v), 31u) < 5) continue;
+        for (int iy = 0; iy < 6; ++iy) {
+            if (!((S5 >> L[iy]) & 1)) continue;
+            const uint32_t S4 = S5 & ~(1u << L[iy]);
+            if (!fits(S4, 4) || gf2_rank(v, vals(S4, v), 15u) < 4) continue;
+            for (int iz = 0; iz < 6; ++iz) {
+                if (!((S4 >> L[iz]) & 1)) continue;
+                const uint32_t S3 = S4 & ~(1u << L[iz]);
+                if (!fits(S3, 3) || gf2_rank(v, vals(S3, v), 7u) < 3) continue;
+                int o = 0;
+                for (int i = 0; i < nr; ++i)
+                    if ((S3 >> req[i]) & 1) order[o++] = req[i];
+                for (int i = 0; i < 6; ++i)
+                    if (((S3 & ~rmask) >> L[i]) & 1) order[o++] = L[i];
+                order[o++] = L[iz];
+                order[o++] = L[iy];
+                order[o++] = L[ix];
+                return true;
+            }
+        }
+    }
+    return false;
+}
+
+static void choose_swizzle(int k, CircuitPlan &P, PassArgs &pa, const int *ld, int nld, const int *st,
+                           int nst) {
+    uint32_t sv[16];
+    for (int j = 0; j < 16; ++j) sv[j] = j < k ? 1u << (j % 6) : 0u;
+    const int np = pa.nphase;
+    std::vector<int32_t> order(6 * std::max(np, 1));
+    std::vector<char> ok(std::max(np, 1), 0);
+    auto req_of = [&](int i, const int *&req) {
+        if (i == 0) {
+            req = ld;
+            return std::min(nld, 6);
+        }
+        if (i == np - 1) {
+            req = st;
+            return std::min(nst, 6);
+        }
+        req = nullptr;
+        return 0;
+    };
+    auto check = [&](int i) {
+        const int *req;
+        const int nr = req_of(i, req);
+        return lane_chain(P.phases[pa.phase0 + i].lane, req, nr, sv, &order[6 * i]);
+    };
+    if (np >= 2) {
+        int score = 0;
+        for (int i = 0; i < np; ++i) score += ok[i] = check(i);
+        // local search: change one tile bit's value, keep it unless fewer
+        // phases meet the condition (deterministic generator)
+        uint64_t rs = 0x9E3779B97F4A7C15ull ^ ((uint64_t)pa.phase0 << 17) ^ (uint64_t)k;
+        auto rnd = [&]() {
+            rs ^= rs << 13;
+            rs ^= rs >> 7;
+            rs ^= rs << 17;
+            return rs;
+        };
+        for (int it = 0; it < 4000 && score < np; ++it) {
+            int bad = (int)(rnd() % (uint64_t)(np - score));
+            int fi = 0;
+            for (; fi < np; ++fi)
+                if (!ok[fi] && bad-- == 0) break;
+            const int t = P.phases[pa.phase0 + fi].lane[rnd() % 6];
+            const uint32_t old = sv[t];
+            sv[t] = t < 6 ? 1u + (uint32_t)(rnd() % 63) : (uint32_t)(rnd() % 64);
+            if (t < 6 && gf2_rank(sv, 6, 63u) < 6) {
+                sv[t] = old;
+                continue;
+            }
+            std::vector<char> nok(ok);
+            int ns = score;
+            std::vector<int32_t> keep(order);
+            for (int i = 0; i < np; ++i) {
+                const int32_t *L = P.phases[pa.phase0 + i].lane;
+                bool has = false;
+                for (int b = 0; b < 6; ++b) has |= L[b] == t;
+                if (!has) continue;
+                ns -= nok[i];
+                ns += nok[i] = check(i);
+            }
+            if (ns >= score) {
+                score = ns;
+                ok.swap(nok);
+            } else {
+                sv[t] = old;
+                order.swap(keep);
+            }
+        }
+        for (int i = 0; i < np; ++i)
+            if (ok[i])
+                for (int b = 0; b < 6; ++b) P.phases[pa.phase0 + i].lane[b] = order[6 * i + b];
+    }
+    for (int j = 0; j < 16; ++j) pa.swz[j] = j >= k ? 0 : (int32_t)(j < 6 ? sv[j] : (1u << j) ^ sv[j]);
+    for (int i = 0; i < np; ++i) {
+        PhaseDesc &D = P.phases[pa.phase0 + i];
+        for (int b = 0; b < 8; ++b) {
+            D.rsl[b] = pa.swz[D.reg[b] & 15];
+            D.lsl[b] = b < 6 ? pa.swz[D.lane[b] & 15] : 0;
+            D.wsl[b] = pa.swz[D.wave[b] & 15];
+        }
+    }
+}
+
 std::string plan_circuit(int n, int g, const std::vector<GateN> &gates, svq_sched sched, int k,
                          int rb, int c, const std::vector<int> &pos0, CircuitPlan &out,
                          bool relayout) {
@@ -928,6 +1093,7 @@ std::string plan_circuit(int n, int g, const std::vector<GateN> &gates, svq_sche
         pa.phase0 = (int)out.phases.size();
         plan_phases(keff, rb, l3, out, ld, nld, st, nst);
         pa.nphase = (int)out.phases.size() - pa.phase0;
+        choose_swizzle(keff, out, pa, ld, nld, st, nst);
     };
     for (const L1Tile &T : tiles) {
         if (local_set(lay, nL) != T.local) {

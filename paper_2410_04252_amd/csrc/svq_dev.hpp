@@ -90,6 +90,11 @@ struct PhaseDesc {
     int32_t lane[8];  // tile-local bit of lane bit b (6 used)
     int32_t wave[8];  // tile-local bit of wave bit b
     int32_t op0, nop;
+    // LDS slot contribution of register, lane and wave bit b under the pass's
+    // slot map (PassArgs::swz of the tile bit), stored here so that a
+    // transpose reads them with the phase instead of through a second,
+    // dependent lookup
+    int32_t rsl[8], lsl[8], wsl[8];
 };
 
 struct PassArgs {
@@ -104,6 +109,8 @@ struct PassArgs {
     int32_t tphys_out[16]; // physical bit of tile-local bit j when stored: a
                            // permutation of tphys (the same addresses), so a
                            // pass may relabel its tile's positions in place
+    int32_t swz[16];       // LDS slot of tile-local index t: the XOR of swz[j]
+                           // over the set bits j of t (a bijection of the tile)
 };
 
 // Read-only Pauli pass (EVC) and H|psi> pass.
@@ -203,6 +210,7 @@ struct BatchStage {
 
 struct BatchPass {
     int32_t tphys[16];   // physical bit of tile-local bit j
+    int32_t swz[16];     // LDS slot map, as PassArgs::swz
     int32_t phase0, nphase;
     int32_t pad[2];
 };
