@@ -244,6 +244,22 @@ def qr_trend(P, W):
                 adhoc=P.sv_plan_ops(30, 25, ops, P.PLAN_ADHOC)["n_qr"])
 
 
+def comm_cost_sweep(P, W):
+    """eq. comm_cost on the host planner: GateFabric with 4n layers (block
+    operators) on 32 PEs, g = 5 with 3 intra-node and 2 inter-node PE bits,
+    for flat and hierarchical tiling, at w_inter / w_intra = 10 and 30."""
+    out = {}
+    for n in (30, 36):
+        ops = W.block_ops(n, 4 * n)
+        row = {}
+        for name, method in (("flat", P.PLAN_FLAT), ("hierarchical", P.PLAN_HIERARCHICAL)):
+            ni, ne, c10 = P.sv_qr_cost(n, n - 5, 3, ops, method, 1.0, 10.0)
+            c30 = P.sv_qr_cost(n, n - 5, 3, ops, method, 1.0, 30.0)[2]
+            row[name] = dict(n_intra=ni, n_inter=ne, cost_w10=c10, cost_w30=c30)
+        out[str(n)] = row
+    return out
+
+
 def measure_qsu_evc(P, W, torch, st, ham, args):
     """The QSU-based comparison method on the first qsu_terms strings (index
     order): each string applied as a gate into psi' (one elementwise pass per
@@ -740,6 +756,7 @@ def main():
         log(f"[bench] plain device copy {copy_gbs:.0f} GB/s; gate pass at "
             f"{res['roofline']['frac_of_copy'] * 100:.1f}% of it")
         res["qsu"]["qr_trend_30q_120_layers"] = qr_trend(P, W)
+        res["qsu"]["comm_cost_32pe"] = comm_cost_sweep(P, W)
     c128 = None if (args.no_c128 or res["dtype"] != "c64") else measure_c128(P, W, torch, args)
     grad = None if args.no_grad else measure_grad(P, W, torch, args)
     legs = None if args.no_legs else measure_legs(P, W, torch, args)

@@ -349,6 +349,22 @@ svq_status sv_plan_ops(int n, int n_local, const uint64_t *targets, int m, int m
                        int n_intra, int fill_highest, int32_t *order_out, uint64_t *local_out,
                        uint64_t *intra_out, int32_t *n_qr_out, int32_t *n_inter_out);
 
+/* eq. comm_cost: Cost = w_intra * N_intra + w_inter * N_inter over the
+ * reorders of a level-1 plan (method as in sv_plan_ops) on a cluster whose
+ * g = n - n_local PE bits split into n_intra intra-node bits (positions
+ * n_local .. n_local + n_intra - 1) and g - n_intra inter-node bits
+ * (fig:qr_types: an inter reorder moves a qubit on or off an inter-node bit).
+ * Hierarchical tiling (method 2) tracks Q_intra and Q_inter itself.  For the
+ * other methods the paper does not say where evicted qubits go: each reorder
+ * swaps its incoming qubits with its outgoing ones pairwise in ascending order
+ * of position (the ad hoc method's own pairing), and counts as inter when an
+ * incoming qubit leaves an inter position.  Weights
+ * must be finite and non-negative (the paper takes w_inter tens of times
+ * w_intra).  Host only.  Errors: EINVAL. */
+svq_status sv_qr_cost(int n, int n_local, int n_intra, const uint64_t *targets, int m, int method,
+                      int fill_highest, double w_intra, double w_inter, int32_t *n_intra_out,
+                      int32_t *n_inter_out, double *cost_out);
+
 /* A plain streaming copy of device memory (16-byte accesses, asynchronous on
  * the stream): the reference against which pass bandwidths and the HBM
  * traffic counters are calibrated.  bytes must be a multiple of 16; the

@@ -164,6 +164,60 @@ def hierarchical_tiling(n, targets, nL, n_intra, fill="lowest"):
     return order, M, tiles, events
 
 
+def qr_kinds_by_position(M, n, nL, n_intra):
+    """Intra and inter reorders (fig:qr_types) of a flat or ad hoc plan's
+    local-set sequence M on a cluster whose global positions nL .. nL+n_intra-1
+    are intra-node PE bits and the rest inter-node ones.  Reading (the paper
+    does not say where such a plan puts the qubits it evicts): a reorder swaps
+    its incoming qubits with its outgoing ones pairwise in ascending order of
+    position, as the ad hoc method does, and is inter when an incoming qubit
+    comes from an inter position.  Returns (N_intra, N_inter)."""
+    pos = list(range(n))
+    prev = frozenset(range(nL))
+    n_in = n_out = 0
+    for m in M:
+        m = frozenset(m)
+        if m == prev:
+            continue
+        incoming = sorted(m - prev, key=lambda q: pos[q])
+        outgoing = sorted(prev - m, key=lambda q: pos[q])
+        vacated = [pos[q] for q in incoming]
+        freed = [pos[q] for q in outgoing]
+        if any(p >= nL + n_intra for p in vacated):
+            n_out += 1
+        else:
+            n_in += 1
+        for q, p in zip(outgoing, vacated):
+            pos[q] = p
+        for q, p in zip(incoming, freed):
+            pos[q] = p
+        prev = m
+    return n_in, n_out
+
+
+def hierarchical_kinds(events, n, nL, n_intra):
+    """(N_intra, N_inter) of hierarchical tiling's remaps (Alg. 4): a remap is
+    a reorder when it changes Q_intra or Q_inter (and so Q_L); it is inter when
+    Q_inter changes."""
+    prev = (frozenset(range(nL, nL + n_intra)), frozenset(range(nL + n_intra, n)))
+    n_in = n_out = 0
+    for _, kind, qi, qe in events:
+        cur = (frozenset(qi), frozenset(qe))
+        if cur == prev:
+            continue
+        if kind == "inter":
+            n_out += 1
+        else:
+            n_in += 1
+        prev = cur
+    return n_in, n_out
+
+
+def comm_cost(n_intra, n_inter, w_intra, w_inter):
+    """eq. comm_cost: weighted count of intra and inter reorders."""
+    return w_intra * n_intra + w_inter * n_inter
+
+
 def n_qr(M, nL):
     """eq. n_qr: number of positions whose local set differs from the previous
     one, starting from {0..n_L-1}."""

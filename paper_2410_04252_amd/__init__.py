@@ -53,7 +53,7 @@ EXPORTS = ("sv_create", "sv_destroy", "sv_set_basis", "sv_set_amplitudes", "sv_g
            "sv_get_layout", "sv_plan_dump", "sv_device_ptr", "sv_apply_circuit",
            "sv_apply_circuit_static", "sv_qr_permute",
            "sv_expectation", "sv_expectation_qsu", "sv_apply_hamiltonian", "sv_grad", "sv_param_shift_grad", "sv_plan_circuit",
-           "sv_plan_circuit_json", "sv_plan_paulis", "sv_plan_ops", "sv_tune_circuit", "sv_tune_paulis",
+           "sv_plan_circuit_json", "sv_plan_paulis", "sv_plan_ops", "sv_qr_cost", "sv_tune_circuit", "sv_tune_paulis",
            "sv_batch_tune", "sv_tune_save", "sv_tune_load", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
            "sv_batch_destroy", "sv_device_copy", "sv_last_error")
 
@@ -115,6 +115,8 @@ def _load():
     L.sv_plan_ops.argtypes = [c_int, c_int, POINTER(c_uint64), c_int, c_int, c_int, c_int,
                               POINTER(c_int32), POINTER(c_uint64), POINTER(c_uint64),
                               POINTER(c_int32), POINTER(c_int32)]
+    L.sv_qr_cost.argtypes = [c_int, c_int, c_int, POINTER(c_uint64), c_int, c_int, c_int, c_double,
+                             c_double, POINTER(c_int32), POINTER(c_int32), POINTER(c_double)]
     L.sv_profile.argtypes = [vp, c_int]
     L.sv_profile_read.argtypes = [vp, c_int, POINTER(c_int), POINTER(c_double)]
     L.sv_device_copy.argtypes = [vp, vp, c_size_t, vp]
@@ -377,6 +379,16 @@ def sv_plan_ops(n, n_local, targets, method, n_intra=0, fill_highest=False):
                            intra, byref(nqr), byref(ninter)))
     return dict(order=list(order)[:m], local=list(loc)[:m], intra=list(intra)[:m],
                 n_qr=nqr.value, n_inter=ninter.value)
+
+
+def sv_qr_cost(n, n_local, n_intra, targets, method, w_intra=1.0, w_inter=10.0, fill_highest=False):
+    """eq. comm_cost of a level-1 plan (host only): (N_intra, N_inter, cost)."""
+    m = len(targets)
+    tm = (c_uint64 * max(1, m))(*[sum(1 << q for q in t) for t in targets])
+    ni, ne, cost = c_int32(), c_int32(), c_double()
+    _check(lib.sv_qr_cost(n, n_local, n_intra, tm, m, method, int(fill_highest), w_intra, w_inter,
+                          byref(ni), byref(ne), byref(cost)))
+    return ni.value, ne.value, cost.value
 
 
 def sv_plan_paulis(n, g, ham, sched, tile_k=0):

@@ -1413,31 +1413,47 @@ svq_status sv_plan_circuit(int n, int g, const svq_gate *gates, int m, svq_sched
     return SVQ_OK;
 }
 
-svq_status sv_plan_ops(int n, int n_local, const uint64_t *targets, int m, int method,
-                       int n_intra, int fill_highest, int32_t *order_out, uint64_t *local_out,
-                       uint64_t *intra_out, int32_t *n_qr_out, int32_t *n_inter_out) {
+// Level-1 tiles of sv_plan_ops / sv_qr_cost (arguments already checked).
+static std::vector<L1Tile> plan_level1(int n, int n_local, const std::vector<uint64_t> &t, int method,
+                                       int n_intra, int fill_highest, std::vector<int> &kinds,
+                                       std::vector<uint64_t> &intra) {
+    const int m = (int)t.size();
+    std::vector<int> pos(n);
+    for (int q = 0; q < n; ++q) pos[q] = q;
+    if (method == 0) return ad_hoc(n, n_local, t, depth_order(t), pos);
+    if (method == 1) return flat_tiling(n, n_local, t, pos);
+    if (method == 3) {
+        std::vector<int> ord(m);
+        for (int i = 0; i < m; ++i) ord[i] = i;
+        return ad_hoc(n, n_local, t, ord, pos);
+    }
+    return hierarchical_tiling(n, n_local, n_intra, t, fill_highest != 0, kinds, intra);
+}
+
+static svq_status check_ops(int n, int n_local, const uint64_t *targets, int m, int method, int n_intra,
+                            std::vector<uint64_t> &t) {
     if (n < 1 || n > 64 || n_local < 1 || n_local > n || m < 0 || (m > 0 && !targets))
         return fail(SVQ_EINVAL, "bad arguments");
     if (method < 0 || method > 3) return fail(SVQ_EINVAL, "method must be 0, 1, 2 or 3");
-    if (method == 2 && (n_intra < 0 || n_local + n_intra > n)) return fail(SVQ_EINVAL, "bad n_intra");
+    if (n_intra < 0 || n_local + n_intra > n) return fail(SVQ_EINVAL, "bad n_intra");
     const uint64_t full = n >= 64 ? ~0ULL : ((1ULL << n) - 1);
-    std::vector<uint64_t> t(targets, targets + m);
+    t.assign(targets, targets + m);
     for (uint64_t v : t)
         if ((v & ~full) || __builtin_popcountll(v) > n_local)
             return fail(SVQ_EINVAL, "operator target set out of range or wider than the local set");
-    std::vector<int> pos(n);
-    for (int q = 0; q < n; ++q) pos[q] = q;
-    std::vector<L1Tile> tiles;
+    return SVQ_OK;
+}
+
+svq_status sv_plan_ops(int n, int n_local, const uint64_t *targets, int m, int method,
+                       int n_intra, int fill_highest, int32_t *order_out, uint64_t *local_out,
+                       uint64_t *intra_out, int32_t *n_qr_out, int32_t *n_inter_out) {
+    std::vector<uint64_t> t;
+    if (method != 2) n_intra = 0;
+    const svq_status rc = check_ops(n, n_local, targets, m, method, n_intra, t);
+    if (rc != SVQ_OK) return rc;
     std::vector<int> kinds;
     std::vector<uint64_t> intra;
-    if (method == 0) tiles = ad_hoc(n, n_local, t, depth_order(t), pos);
-    else if (method == 1) tiles = flat_tiling(n, n_local, t, pos);
-    else if (method == 3) {
-        std::vector<int> ord(m);
-        for (int i = 0; i < m; ++i) ord[i] = i;
-        tiles = ad_hoc(n, n_local, t, ord, pos);
-    }
-    else tiles = hierarchical_tiling(n, n_local, n_intra, t, fill_highest != 0, kinds, intra);
+    const std::vector<L1Tile> tiles = plan_level1(n, n_local, t, method, n_intra, fill_highest, kinds, intra);
     int x = 0, nqr = 0, ninter = 0;
     uint64_t prev = (1ULL << n_local) - 1;
     for (size_t ti = 0; ti < tiles.size(); ++ti) {
@@ -1453,6 +1469,62 @@ svq_status sv_plan_ops(int n, int n_local, const uint64_t *targets, int m, int m
     }
     if (n_qr_out) *n_qr_out = nqr;
     if (n_inter_out) *n_inter_out = ninter;
+    return SVQ_OK;
+}
+
+svq_status sv_qr_cost(int n, int n_local, int n_intra, const uint64_t *targets, int m, int method,
+                      int fill_highest, double w_intra, double w_inter, int32_t *n_intra_out,
+                      int32_t *n_inter_out, double *cost_out) {
+    std::vector<uint64_t> t;
+    const svq_status rc = check_ops(n, n_local, targets, m, method, n_intra, t);
+    if (rc != SVQ_OK) return rc;
+    if (!std::isfinite(w_intra) || !std::isfinite(w_inter) || w_intra < 0 || w_inter < 0)
+        return fail(SVQ_EINVAL, "weights must be finite and non-negative");
+    std::vector<int> kinds;
+    std::vector<uint64_t> intra;
+    const std::vector<L1Tile> tiles = plan_level1(n, n_local, t, method, n_intra, fill_highest, kinds, intra);
+    // Positions n_local .. n_local + n_intra - 1 are the intra-node PE bits,
+    // those above the inter-node ones.  A flat or ad hoc reorder swaps its
+    // incoming qubits with its outgoing ones pairwise in ascending order of
+    // position (the ad hoc method's own pairing); it is an inter reorder when
+    // an incoming qubit leaves an inter position.  The
+    // hierarchical tiling tracks Q_intra itself: its reorder is inter when the
+    // set of inter qubits changes.
+    std::vector<int> pos(n);
+    for (int q = 0; q < n; ++q) pos[q] = q;
+    uint64_t prev = (1ULL << n_local) - 1;
+    uint64_t prev_intra = ((1ULL << n_intra) - 1) << n_local;
+    int ni = 0, ne = 0;
+    for (size_t ti = 0; ti < tiles.size(); ++ti) {
+        const uint64_t cur = tiles[ti].local;
+        bool inter = false;
+        if (method == 2) {
+            if (cur == prev && intra[ti] == prev_intra) continue;
+            inter = kinds[ti] != 0;
+            prev_intra = intra[ti];
+        } else {
+            if (cur == prev) continue;
+            std::vector<int> in, out, vac;
+            for (int q = 0; q < n; ++q) {
+                if (((cur >> q) & 1) && !((prev >> q) & 1)) in.push_back(q);
+                if (((prev >> q) & 1) && !((cur >> q) & 1)) out.push_back(q);
+            }
+            auto by_pos = [&](int a, int b) { return pos[a] < pos[b]; };
+            std::sort(in.begin(), in.end(), by_pos);
+            std::sort(out.begin(), out.end(), by_pos);
+            std::vector<int> loc;
+            for (int q : in) vac.push_back(pos[q]);
+            for (int q : out) loc.push_back(pos[q]);
+            for (int p : vac) inter |= p >= n_local + n_intra;
+            for (size_t i = 0; i < out.size(); ++i) pos[out[i]] = vac[i];
+            for (size_t i = 0; i < in.size(); ++i) pos[in[i]] = loc[i];
+        }
+        ++(inter ? ne : ni);
+        prev = cur;
+    }
+    if (n_intra_out) *n_intra_out = ni;
+    if (n_inter_out) *n_inter_out = ne;
+    if (cost_out) *cost_out = w_intra * ni + w_inter * ne;
     return SVQ_OK;
 }
 

@@ -154,3 +154,87 @@ def test_evc_qr_sweep_alg6_vs_qsu_based(P):
         assert lazy < qsu["n_qr"]
         ratios.append(qsu["n_qr"] / max(1, lazy))
     assert ratios[-1] > 20
+
+
+# ---- eq. comm_cost: intra and inter reorders --------------------------------
+
+def test_qr_kinds_oracle_hand_example():
+    """n = 6, n_L = 3, one intra PE bit (position 3), inter bits 4 and 5.
+    {0,1,2} -> {0,1,3}: qubit 3 comes from the intra position (intra), qubit 2
+    takes position 3.  -> {0,1,4}: qubit 4 comes from inter position 4
+    (inter), qubit 3 goes there.  -> {0,1,2}: qubit 2 comes from position 3
+    (intra)."""
+    M = [{0, 1, 2}, {0, 1, 3}, {0, 1, 4}, {0, 1, 2}]
+    assert S.qr_kinds_by_position(M, 6, 3, 1) == (2, 1)
+    assert S.qr_kinds_by_position(M, 6, 3, 0) == (0, 3)     # every PE bit inter
+    assert S.qr_kinds_by_position(M, 6, 3, 3) == (3, 0)     # every PE bit intra
+    assert S.comm_cost(2, 1, 1.0, 10.0) == 12.0
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_qr_kinds_oracle_against_ad_hoc_transpositions(seed):
+    """The ad hoc method records its own position pairs: a reorder is inter
+    exactly when one of its pairs touches an inter position."""
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(8, 16))
+    nL = n - int(rng.integers(2, 5))
+    n_intra = int(rng.integers(0, n - nL + 1))
+    ops = [tuple(int(v) for v in rng.choice(n, size=int(rng.integers(1, 4)), replace=False))
+           for _ in range(60)]
+    _, M, qrs = S.ad_hoc(n, ops, nL)
+    want_inter = sum(1 for pairs in qrs if any(max(a, b) >= nL + n_intra for a, b in pairs))
+    assert S.qr_kinds_by_position(M, n, nL, n_intra) == (len(qrs) - want_inter, want_inter)
+
+
+def test_qr_cost_figure_counts(P):
+    gold = json.load(open(os.path.join(GOLD, "hierarchical_tiling_fig.json")))
+    n, nL, ni = gold["n"], gold["n_L"], gold["n_intra"]
+    pc = gold["paper_counts"]
+    fl = P.sv_qr_cost(n, nL, ni, _fig_ops(), P.PLAN_FLAT, 1.0, 20.0)
+    hi = P.sv_qr_cost(n, nL, ni, _fig_ops(), P.PLAN_HIERARCHICAL, 1.0, 20.0, fill_highest=True)
+    assert fl[:2] == (pc["flat"]["intra"], pc["flat"]["inter"])
+    assert hi[:2] == (pc["hierarchical"]["intra"], pc["hierarchical"]["inter"])
+    assert hi[2] < fl[2] == 60.0
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_qr_cost_matches_oracle(P, seed):
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(8, 18))
+    nL = n - int(rng.integers(2, 6))
+    n_intra = int(rng.integers(0, n - nL + 1))
+    ops = [tuple(int(v) for v in rng.choice(n, size=int(rng.integers(1, min(5, nL) + 1)), replace=False))
+           for _ in range(int(rng.integers(10, 90)))]
+    w = (1.0, float(rng.integers(10, 40)))
+    _, M, _ = S.flat_tiling(n, ops, nL)[:3]
+    want = S.qr_kinds_by_position(M, n, nL, n_intra)
+    got = P.sv_qr_cost(n, nL, n_intra, ops, P.PLAN_FLAT, *w)
+    assert got[:2] == want and got[2] == S.comm_cost(*want, *w)
+    _, M, _ = S.ad_hoc(n, ops, nL)
+    assert P.sv_qr_cost(n, nL, n_intra, ops, P.PLAN_ADHOC, *w)[:2] == \
+        S.qr_kinds_by_position(M, n, nL, n_intra)
+    for fill in ("lowest", "highest"):
+        ev = S.hierarchical_tiling(n, ops, nL, n_intra, fill=fill)[3]
+        want = S.hierarchical_kinds(ev, n, nL, n_intra)
+        got = P.sv_qr_cost(n, nL, n_intra, ops, P.PLAN_HIERARCHICAL, *w, fill_highest=fill == "highest")
+        assert got[:2] == want and got[2] == S.comm_cost(*want, *w)
+
+
+@pytest.mark.parametrize("n", [30, 36])
+def test_comm_cost_gatefabric_sweep(P, n):
+    """eq. comm_cost on the evaluation's GateFabric configuration (4n layers,
+    block operators, 32 PEs: g = 5 with 8 GPUs per node, so 3 intra and 2
+    inter PE bits): the library's N_intra / N_inter equal the oracle's for
+    flat and hierarchical tiling; the hierarchical method makes fewer inter
+    reorders, and its weighted cost is lower once w_inter / w_intra reaches
+    tens (30)."""
+    g, n_intra = 5, 3
+    nL = n - g
+    ops = W.block_ops(n, 4 * n)
+    _, M, _ = S.flat_tiling(n, ops, nL)[:3]
+    fl = S.qr_kinds_by_position(M, n, nL, n_intra)
+    hi = S.hierarchical_kinds(S.hierarchical_tiling(n, ops, nL, n_intra)[3], n, nL, n_intra)
+    assert P.sv_qr_cost(n, nL, n_intra, ops, P.PLAN_FLAT)[:2] == fl
+    assert P.sv_qr_cost(n, nL, n_intra, ops, P.PLAN_HIERARCHICAL)[:2] == hi
+    assert hi[1] < fl[1]
+    assert S.comm_cost(*hi, 1.0, 30.0) < S.comm_cost(*fl, 1.0, 30.0)
