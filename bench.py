@@ -534,7 +534,8 @@ def measure_legs(P, W, torch, args):
 def measure_batch(P, W, torch, args):
     """256 independent instances (n uniform in 10..22, 6 fabric layers, 200
     JW-like terms): QSU + EVC + adjoint gradient of all of them in one
-    persistent, graph-captured launch, against a one-at-a-time loop."""
+    captured graph (one launch per stage level and item type), against a
+    one-at-a-time loop."""
     import numpy as np
     inst = [(d["circuit"], d["ham"]) for d in W.batch_instances()]
     ninst = len(inst)
@@ -550,6 +551,7 @@ def measure_batch(P, W, torch, args):
     t0 = time.perf_counter()
     b = P.Batch(inst)
     create_ms = (time.perf_counter() - t0) * 1e3
+    batch_bytes, n_stages, n_items = b.info()
     b.run()                       # first run captures the graph
     torch.cuda.synchronize()
     reps = 5
@@ -584,8 +586,13 @@ def measure_batch(P, W, torch, args):
     loop_ms = done[-1]
     log(f"[bench] batch {run_ms:.2f} ms ({ninst / run_ms * 1e3:.0f} inst/s, p50 {np.percentile(lat, 50):.2f} "
         f"p99 {np.percentile(lat, 99):.2f} ms); one at a time {loop_ms:.1f} ms")
+    gbs = batch_bytes / (run_ms * 1e-3) / 1e9
+    log(f"[bench] batch algorithmic traffic {batch_bytes / 1e9:.1f} GB per run: {gbs:.0f} GB/s "
+        f"({gbs / HBM_PEAK_GBS * 100:.1f}% of HBM peak), {n_stages} stages, {n_items} items")
     return dict(workload="batch256", instances=ninst, create_ms=create_ms, tuned=tuned,
-                persistent_ms=run_ms, instances_per_s=ninst / run_ms * 1e3,
+                mode="level-synchronous launches in one graph", batch_ms=run_ms,
+                algorithmic_bytes=batch_bytes, algorithmic_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
+                stages=n_stages, items=n_items, instances_per_s=ninst / run_ms * 1e3,
                 latency_p50_ms=float(np.percentile(lat, 50)),
                 latency_p99_ms=float(np.percentile(lat, 99)),
                 loop_ms=loop_ms, loop_instances_per_s=ninst / loop_ms * 1e3,

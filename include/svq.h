@@ -273,12 +273,16 @@ svq_status sv_plan_paulis(int n, int g, const svq_pauli *terms, int n_terms, svq
 /* ---- batched VQE -------------------------------------------------------
  * Many independent instances (each its own circuit, angles and Hamiltonian,
  * qubit counts 10..26, all qubits local: no emulated global qubits, so no
- * reordering) evaluated in one persistent kernel launch that is captured
- * once in a HIP graph and replayed per call.  Every stage of an instance
- * (psi0, each gate pass, each H|psi> pass, <psi|H psi>, each reverse adjoint
- * pass, the final FP64 sums) is cut into 2^10-amplitude tiles; single-wave
- * blocks pull (instance, stage, tile) items from one device queue and wait,
- * with a bounded spin, for the instance's previous stage.
+ * reordering) evaluated by one HIP graph that is captured once and replayed
+ * per call.  Every stage of an instance (psi0, each gate pass, each H|psi>
+ * pass, <psi|H psi>, each reverse adjoint pass, the final FP64 sums) is cut
+ * into 2^10-amplitude tiles, grouped into items (a range of tiles each).  The
+ * graph holds one launch per (stage level, item type): the k-th stages of all
+ * instances that are gate passes run in one launch, and so on; stream order
+ * carries the dependencies.  With SVQ_BATCH_PERSISTENT=1 in the environment
+ * at creation the graph instead holds one persistent launch whose single-wave
+ * blocks pull items from a device queue and wait, with a bounded spin, for
+ * the instance's previous stage.
  * The plans are built once (the schedule reused across VQE iterations,
  * Section "Scheduling time"); only the angles change per call. */
 typedef struct svq_batch_s *svq_batch;
@@ -296,10 +300,16 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
  * energies_host[n_inst] and grads_host[sum n_theta] (concatenated in instance
  * order) receive E and dE/dtheta; latency_ms_host[n_inst] (nullable) the
  * time from kernel start to the completion of each instance (device clock).
- * Synchronises the stream.  A dependency wait that exceeds its bound returns
- * EHIP and poisons the batch. */
+ * Synchronises the stream.  In the persistent form a dependency wait that
+ * exceeds its bound returns EHIP and poisons the batch. */
 svq_status sv_batch_run(svq_batch b, const double *const *theta, double *energies_host,
                         double *grads_host, double *latency_ms_host);
+/* Shape of a batch: the algorithmic HBM bytes of one run (one write of every
+ * psi, a read and a write of psi per gate pass, of psi and lambda per reverse
+ * pass, a read of psi and a write of lambda per H|psi> pass plus a read of
+ * lambda when it accumulates, and a read of both for the dot), the number of
+ * stages and of work items.  All outputs nullable.  Errors: EINVAL. */
+svq_status sv_batch_info(svq_batch b, double *bytes_per_run, int32_t *n_stages, int32_t *n_items);
 svq_status sv_batch_destroy(svq_batch b);
 
 /* ---- measured tuning ----------------------------------------------------

@@ -55,7 +55,7 @@ EXPORTS = ("sv_create", "sv_destroy", "sv_set_basis", "sv_set_amplitudes", "sv_g
            "sv_expectation", "sv_expectation_qsu", "sv_apply_hamiltonian", "sv_grad", "sv_param_shift_grad", "sv_plan_circuit",
            "sv_plan_circuit_json", "sv_plan_paulis", "sv_plan_ops", "sv_qr_cost", "sv_tune_circuit", "sv_tune_paulis",
            "sv_batch_tune", "sv_tune_save", "sv_tune_load", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
-           "sv_batch_destroy", "sv_device_copy", "sv_last_error")
+           "sv_batch_destroy", "sv_batch_info", "sv_device_copy", "sv_last_error")
 
 
 def _load():
@@ -117,6 +117,7 @@ def _load():
                               POINTER(c_int32), POINTER(c_int32)]
     L.sv_qr_cost.argtypes = [c_int, c_int, c_int, POINTER(c_uint64), c_int, c_int, c_int, c_double,
                              c_double, POINTER(c_int32), POINTER(c_int32), POINTER(c_double)]
+    L.sv_batch_info.argtypes = [vp, POINTER(c_double), POINTER(c_int32), POINTER(c_int32)]
     L.sv_profile.argtypes = [vp, c_int]
     L.sv_profile_read.argtypes = [vp, c_int, POINTER(c_int), POINTER(c_double)]
     L.sv_device_copy.argtypes = [vp, vp, c_size_t, vp]
@@ -580,6 +581,12 @@ class Batch:
             grads.append(g[o:o + k].copy())
             o += k
         return e, grads, lat
+
+    def info(self):
+        """(algorithmic HBM bytes of one run, stages, work items)."""
+        by, ns, ni = c_double(), c_int32(), c_int32()
+        _check(lib.sv_batch_info(self.h, byref(by), byref(ns), byref(ni)))
+        return by.value, ns.value, ni.value
 
     def close(self):
         if self.h is not None and self.h.value:

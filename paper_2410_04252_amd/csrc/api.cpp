@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -1568,6 +1569,9 @@ struct svq_batch_s {
     std::vector<int> op_gate, op_inst;     // gate index / instance of every op
     std::vector<BatchInst> insts;
     int nitems = 0, nstages = 0, total_theta = 0;
+    double bytes_per_run = 0;              // algorithmic HBM bytes of one run
+    bool persistent = false;               // one persistent launch, else level-synchronous
+    std::vector<std::array<int, 3>> groups;   // level-synchronous launches: type, item0, count
     DevBuf arena, items, stages, dinsts, passes, hpasses, phases, d_ops_fwd, d_ops_inv, hgroups,
         hterms, pptr, pgate, epart, gpart, energies, grads, counters, t_done, t_start;
     OpDesc *h_ops_fwd = nullptr, *h_ops_inv = nullptr;   // pinned staging
@@ -1730,6 +1734,15 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
         for (size_t p = cp.passes.size(); p-- > 0;) add(IT_ADJ, I.ntiles, pass_base + (int)p, 0);
         add(IT_FINAL, 1, 0, 0);
         I.nstages = (int)stages.size() - I.stage0;
+        {
+            // one write of psi (init); a gate pass reads and writes psi, its
+            // reverse psi and lambda; an H pass reads psi and writes lambda
+            // (and reads it when accumulating); the dot reads both
+            const double S = 8.0 * (double)(1LL << n);
+            const double hp = (double)pp.hpasses.size();
+            b->bytes_per_run += S * (1.0 + 2.0 * cp.passes.size() + 2.0 * hp + std::max(0.0, hp - 1.0) + 2.0 +
+                                     4.0 * cp.passes.size());
+        }
         inst_stage_count[i] = I.nstages;
         // CSR parameter -> gates (gate indices local to the instance)
         I.pptr_off = (int)pptr.size();
@@ -1752,10 +1765,17 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
     std::vector<BatchItem> items;
     int maxst = 0;
     for (int i = 0; i < n_inst; ++i) maxst = std::max(maxst, inst_stage_count[i]);
+    // Items are level-major (all first stages, then all second stages, ...),
+    // and inside a level grouped by type: the persistent kernel needs every
+    // item's predecessor earlier in the queue, the level-synchronous launches
+    // one contiguous range per (level, type).
     for (int sidx = 0; sidx < maxst; ++sidx)
+      for (int type = IT_INIT; type <= IT_FINAL; ++type) {
+        const int item0 = (int)items.size();
         for (int i = 0; i < n_inst; ++i) {
             if (sidx >= inst_stage_count[i]) continue;
             const BatchStage &st = stages[b->insts[i].stage0 + sidx];
+            if (st.type != type) continue;
             const int nch = st.type == IT_FINAL ? 1 : b->insts[i].nchunks;
             for (int ch = 0; ch < nch; ++ch) {
                 const int t0 = (int)((int64_t)st.ntiles * ch / nch);
@@ -1770,7 +1790,10 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
                 items.push_back(it);
             }
         }
+        if ((int)items.size() > item0) b->groups.push_back({type, item0, (int)items.size() - item0});
+      }
     b->nitems = (int)items.size();
+    b->persistent = env_int("SVQ_BATCH_PERSISTENT", 0) != 0;
     b->ops_inv = b->ops_fwd;
     hipStream_t s = b->stream;
     svq_batch bp = b.get();
@@ -1868,7 +1891,15 @@ svq_status sv_batch_run(svq_batch b, const double *const *theta, double *energie
         BHIPCHK(b, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
         BHIPCHK(b, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
         int grid = 0;
-        hipError_t le = launch_batch(b->args, (int32_t *)b->counters.p, b->nstages + 2, cap, &grid);
+        hipError_t le = hipSuccess;
+        if (b->persistent) {
+            le = launch_batch(b->args, (int32_t *)b->counters.p, b->nstages + 2, cap, &grid);
+        } else {
+            // the error flag stays zero: these launches never wait
+            le = launch_fill_i32((int32_t *)b->counters.p, b->nstages + 2, 0, cap);
+            for (size_t gi = 0; gi < b->groups.size() && le == hipSuccess; ++gi)
+                le = launch_batch_stage(b->args, b->groups[gi][0], b->groups[gi][1], b->groups[gi][2], cap);
+        }
         hipError_t ce = hipStreamEndCapture(cap, &b->graph);
         (void)hipStreamDestroy(cap);
         BHIPCHK(b, le, "launch batch");
@@ -1897,6 +1928,14 @@ svq_status sv_batch_run(svq_batch b, const double *const *theta, double *energie
         for (int i = 0; i < b->n_inst; ++i)
             latency_ms_host[i] = (double)(int64_t)(td[i] - t0) / (double)khz;
     }
+    return SVQ_OK;
+}
+
+svq_status sv_batch_info(svq_batch b, double *bytes_per_run, int32_t *n_stages, int32_t *n_items) {
+    if (!b) return fail(SVQ_EINVAL, "null batch");
+    if (bytes_per_run) *bytes_per_run = b->bytes_per_run;
+    if (n_stages) *n_stages = b->nstages;
+    if (n_items) *n_items = b->nitems;
     return SVQ_OK;
 }
 
@@ -2112,7 +2151,7 @@ svq_status sv_batch_tune(int n_inst, const int32_t *n_qubits, const svq_gate *co
     for (int i = 0; i < n_inst; ++i) total += n_theta ? n_theta[i] : 0;
     std::vector<double> e(n_inst), g(std::max(1, total));
     TuneVal best{0, 0, 1e300};
-    const int chunk_c[] = {16, 32, 64, 128};
+    const int chunk_c[] = {64, 256, 1024, 4096};
     const int low_c[] = {3, 4, 5};
     for (int ch : chunk_c)
         for (int c : low_c) {

@@ -1472,7 +1472,7 @@ static_assert((1 << HTPB) == 64, "one wave per tile");
 __device__ __forceinline__ double wave_sum_d(double v) { return wave_sum(v); }
 
 template <bool ADJ>
-__device__ void gate_item(const BatchArgs &a, const BatchInst &N, const BatchPass &bp, uint32_t tile,
+__device__ __forceinline__ void gate_item(const BatchArgs &a, const BatchInst &N, const BatchPass &bp, uint32_t tile,
                           float2 *lds, int chunk, bool first) {
     using R = float;
     using V = float2;
@@ -1549,7 +1549,7 @@ __device__ void gate_item(const BatchArgs &a, const BatchInst &N, const BatchPas
     if constexpr (ADJ) store_regs<V, R, NR, RB, K, true>(w, lam + base, tpL, mL);
 }
 
-__device__ void hpsi_item(const BatchArgs &a, const BatchInst &N, const BatchHPass &hp, int accumulate,
+__device__ __forceinline__ void hpsi_item(const BatchArgs &a, const BatchInst &N, const BatchHPass &hp, int accumulate,
                           uint32_t tile, float2 *lds) {
     using R = float;
     using V = float2;
@@ -1614,7 +1614,7 @@ __device__ void hpsi_item(const BatchArgs &a, const BatchInst &N, const BatchHPa
 }
 
 // Contiguous tile t of an instance: element t * 2^K + j * 64 + lane.
-__device__ void init_item(const BatchArgs &a, const BatchInst &N, uint32_t tile) {
+__device__ __forceinline__ void init_item(const BatchArgs &a, const BatchInst &N, uint32_t tile) {
     const uint32_t lane = threadIdx.x & 63u;
     float2 *psi = a.arena + N.psi_off;
     const uint64_t idx0 = ((uint64_t)N.psi0_hi << 32) | N.psi0_lo;
@@ -1625,7 +1625,7 @@ __device__ void init_item(const BatchArgs &a, const BatchInst &N, uint32_t tile)
     }
 }
 
-__device__ double dot_tile(const BatchArgs &a, const BatchInst &N, uint32_t tile) {
+__device__ __forceinline__ double dot_tile(const BatchArgs &a, const BatchInst &N, uint32_t tile) {
     const uint32_t lane = threadIdx.x & 63u;
     const float2 *psi = a.arena + N.psi_off;
     const float2 *lam = a.arena + N.lam_off;
@@ -1639,7 +1639,7 @@ __device__ double dot_tile(const BatchArgs &a, const BatchInst &N, uint32_t tile
     return acc;
 }
 
-__device__ void final_item(const BatchArgs &a, const BatchInst &N, int inst) {
+__device__ __forceinline__ void final_item(const BatchArgs &a, const BatchInst &N, int inst) {
     const uint32_t lane = threadIdx.x & 63u;
     double e = 0.0;
     for (int t = lane; t < N.nchunks; t += 64) e += a.epart[N.epart_off + t];
@@ -1723,6 +1723,41 @@ __global__ __launch_bounds__(64) void k_batch(const BatchArgs a) {
     }
 }
 
+// Level-synchronous batch: one launch per (stage level, item type) over the
+// items of that level, block b running item item0 + b to the end.  Stream
+// order between the launches carries every dependency, so no block waits,
+// and each item type gets a kernel of its own (registers and LDS sized for
+// that type alone rather than for the largest of all types).
+template <int TYPE>
+__global__ __launch_bounds__(64) void k_batch_stage(const BatchArgs a, int item0) {
+    constexpr int NLDS = TYPE == IT_ADJ ? (2 << kBatchK) : (TYPE == IT_FWD || TYPE == IT_HPSI) ? (1 << kBatchK) : 1;
+    __shared__ float2 lds[NLDS];
+    const uint32_t lane = threadIdx.x & 63u;
+    const BatchItem I = a.items[item0 + (int)blockIdx.x];
+    const BatchInst &N = a.insts[I.inst];
+    const BatchStage S = a.stages[N.stage0 + I.stage];
+    if constexpr (TYPE == IT_INIT) {
+        if (item0 == 0 && blockIdx.x == 0 && lane == 0) *a.t_start = __builtin_amdgcn_s_memrealtime();
+    }
+    double dacc = 0.0;
+    for (int k = 0; k < I.ntile; ++k) {
+        const uint32_t tile = (uint32_t)(I.tile0 + k);
+        if constexpr (TYPE == IT_INIT) batch::init_item(a, N, tile);
+        else if constexpr (TYPE == IT_FWD) batch::gate_item<false>(a, N, a.passes[S.desc], tile, lds, I.chunk, k == 0);
+        else if constexpr (TYPE == IT_HPSI) batch::hpsi_item(a, N, a.hpasses[S.desc], S.accumulate, tile, lds);
+        else if constexpr (TYPE == IT_DOT) dacc += batch::dot_tile(a, N, tile);
+        else if constexpr (TYPE == IT_ADJ) batch::gate_item<true>(a, N, a.passes[S.desc], tile, lds, I.chunk, k == 0);
+    }
+    if constexpr (TYPE == IT_DOT) {
+        dacc = wave_sum(dacc);
+        if (lane == 0) a.epart[N.epart_off + I.chunk] = dacc;
+    }
+    if constexpr (TYPE == IT_FINAL) {
+        batch::final_item(a, N, I.inst);
+        if (lane == 0) a.t_done[I.inst] = __builtin_amdgcn_s_memrealtime();
+    }
+}
+
 __global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
@@ -1738,6 +1773,25 @@ hipError_t launch_batch(const BatchArgs &a, int32_t *counters, int ncounters, hi
     const int grid = per_cu * num_cu();
     if (grid_out) *grid_out = grid;
     hipLaunchKernelGGL(k_batch, dim3(grid), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_stage(const BatchArgs &a, int type, int item0, int nitem, hipStream_t s) {
+    if (nitem <= 0) return hipSuccess;
+    switch (type) {
+    case IT_INIT: hipLaunchKernelGGL(k_batch_stage<IT_INIT>, dim3(nitem), dim3(64), 0, s, a, item0); break;
+    case IT_FWD: hipLaunchKernelGGL(k_batch_stage<IT_FWD>, dim3(nitem), dim3(64), 0, s, a, item0); break;
+    case IT_HPSI: hipLaunchKernelGGL(k_batch_stage<IT_HPSI>, dim3(nitem), dim3(64), 0, s, a, item0); break;
+    case IT_DOT: hipLaunchKernelGGL(k_batch_stage<IT_DOT>, dim3(nitem), dim3(64), 0, s, a, item0); break;
+    case IT_ADJ: hipLaunchKernelGGL(k_batch_stage<IT_ADJ>, dim3(nitem), dim3(64), 0, s, a, item0); break;
+    case IT_FINAL: hipLaunchKernelGGL(k_batch_stage<IT_FINAL>, dim3(nitem), dim3(64), 0, s, a, item0); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -71,5 +71,9 @@ hipError_t launch_fill_basis(bool dbl, void *psi, uint64_t N, uint64_t idx, hipS
 // Reset counters (fill kernel) and launch the persistent batch kernel.
 hipError_t launch_batch(const BatchArgs &a, int32_t *counters, int ncounters, hipStream_t s,
                         int *grid_out);
+// p[0, n) = v with a fill kernel (no memset node in a captured graph).
+hipError_t launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s);
+// One level-synchronous launch: items [item0, item0 + nitem), all of one type.
+hipError_t launch_batch_stage(const BatchArgs &a, int type, int item0, int nitem, hipStream_t s);
 
 }  // namespace svq

@@ -1,5 +1,5 @@
-"""Batched VQE (one persistent, graph-captured launch) against the oracle and
-against one-at-a-time evaluation."""
+"""Batched VQE (one graph of level-synchronous launches, or one persistent
+launch) against the oracle and against one-at-a-time evaluation."""
 import os
 
 import numpy as np
@@ -72,16 +72,38 @@ def test_batch_equals_one_at_a_time(P):
     b.close()
 
 
+def test_persistent_batch_matches_level_synchronous(P, monkeypatch):
+    """The persistent form (one launch, a device queue, bounded waits) gives
+    the level-synchronous form's energies and gradients."""
+    inst = _instances(12, 10, 15, 2500)
+    print("persistent vs level-synchronous", flush=True)
+    b = P.Batch(inst)
+    e, grads, _ = b.run()
+    b.close()
+    monkeypatch.setenv("SVQ_BATCH_PERSISTENT", "1")
+    b = P.Batch(inst)
+    e2, grads2, lat2 = b.run()
+    b.close()
+    for i, (c, h) in enumerate(inst):
+        ok, rel = energy_ok(e2[i], e[i], None, h, "c64")
+        assert ok, (i, rel)
+        ok, grel = grad_ok(grads2[i], grads[i], h, "c64")
+        assert ok, (i, grel)
+    assert np.all(lat2 > 0)
+
+
 def test_batch_bounded_wait_expires_cleanly(P):
     """A spin limit of zero (set from the host) makes every unmet dependency
     wait give up at once: the kernel drains, the call reports EHIP and the
     batch is poisoned, or, if no wait was ever unmet, the results are right."""
     inst = _instances(16, 12, 16, 2900)
     os.environ["SVQ_BATCH_SPIN_LIMIT"] = "0"
+    os.environ["SVQ_BATCH_PERSISTENT"] = "1"
     try:
         b = P.Batch(inst)
     finally:
         del os.environ["SVQ_BATCH_SPIN_LIMIT"]
+        del os.environ["SVQ_BATCH_PERSISTENT"]
     try:
         e, grads, _ = b.run()
     except P.SvqError as err:
