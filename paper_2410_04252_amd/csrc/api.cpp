@@ -1641,8 +1641,15 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
     int64_t arena_elems = 0;
     int epart_total = 0, gpart_total = 0;
     std::vector<int> inst_stage_count(n_inst);
+    b->persistent = env_int("SVQ_BATCH_PERSISTENT", 0) != 0;
+    // Large instances run their gate passes on 2^12-amplitude tiles with
+    // 4-wave blocks (fewer passes, the single-state pass's layout); the
+    // persistent form keeps every stage on 2^10 tiles.
+    const int wide_n = env_int("SVQ_BATCH_WIDE_N", kBatchWideN);
     for (int i = 0; i < n_inst; ++i) {
         const int n = n_qubits[i];
+        const bool wide = !b->persistent && n >= wide_n && n >= kBatchKWide;
+        const int KG = wide ? kBatchKWide : K;
         if (n < K || n > 26) return fail(SVQ_EINVAL, "batch instances need 10 <= n <= 26");
         if (m[i] < 0 || n_theta[i] < 0 || n_terms[i] < 1) return fail(SVQ_EINVAL, "bad instance sizes");
         if (psi0[i] >> n) return fail(SVQ_EINVAL, "psi0 index >= 2^n");
@@ -1652,18 +1659,20 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
         std::vector<int> pos(n);
         for (int q = 0; q < n; ++q) pos[q] = q;
         CircuitPlan cp;
-        err = plan_circuit(n, 0, gn, SVQ_LAZY, K, gate_rb(K), c, pos, cp, false);
+        err = plan_circuit(n, 0, gn, SVQ_LAZY, KG, gate_rb(KG), c, pos, cp, false);
         if (!err.empty()) return fail(SVQ_EINVAL, err);
         PauliPlan pp;
-        err = plan_paulis(n, 0, terms[i], n_terms[i], SVQ_LAZY, K, c, false, pos, pp);
+        err = plan_paulis(n, 0, terms[i], n_terms[i], SVQ_LAZY, KG, c, false, pos, pp);
         if (!err.empty()) return fail(SVQ_EINVAL, err);
-        if (cp.n_qr || pp.n_qr || !pp.wide_groups.empty() || cp.k != K || pp.k != K)
+        if (cp.n_qr || pp.n_qr || !pp.wide_groups.empty() || cp.k != KG || pp.k != KG)
             return fail(SVQ_EUNSUP, "instance " + std::to_string(i) + " needs a reorder or a wide term");
         BatchInst I;
         std::memset(&I, 0, sizeof(I));
         I.n = n;
         I.ntiles = 1 << (n - K);
-        I.nchunks = std::min(I.ntiles, chunks);
+        // every stage type splits into the same nchunks items (the gradient
+        // and energy partial slots are per chunk)
+        I.nchunks = std::min(1 << (n - KG), chunks);
         I.psi_off = arena_elems;
         I.lam_off = arena_elems + (1LL << n);
         arena_elems += 2LL << n;
@@ -1728,11 +1737,13 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
             stages.push_back(st);
         };
         add(IT_INIT, I.ntiles, 0, 0);
-        for (size_t p = 0; p < cp.passes.size(); ++p) add(IT_FWD, I.ntiles, pass_base + (int)p, 0);
-        for (size_t h = 0; h < pp.hpasses.size(); ++h) add(IT_HPSI, I.ntiles, hp_base + (int)h, h > 0);
+        const int gtiles = 1 << (n - KG);
+        for (size_t p = 0; p < cp.passes.size(); ++p) add(wide ? IT_FWD_W : IT_FWD, gtiles, pass_base + (int)p, 0);
+        for (size_t h = 0; h < pp.hpasses.size(); ++h)
+            add(wide ? IT_HPSI_W : IT_HPSI, gtiles, hp_base + (int)h, h > 0);
         add(IT_DOT, I.ntiles, 0, 0);
-        for (size_t p = cp.passes.size(); p-- > 0;) add(IT_ADJ, I.ntiles, pass_base + (int)p, 0);
-        add(IT_FINAL, 1, 0, 0);
+        for (size_t p = cp.passes.size(); p-- > 0;) add(wide ? IT_ADJ_W : IT_ADJ, gtiles, pass_base + (int)p, 0);
+        add(IT_FINAL, n_theta[i] + 1, 0, 0);   // one slot per parameter, one for E
         I.nstages = (int)stages.size() - I.stage0;
         {
             // one write of psi (init); a gate pass reads and writes psi, its
@@ -1770,13 +1781,13 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
     // item's predecessor earlier in the queue, the level-synchronous launches
     // one contiguous range per (level, type).
     for (int sidx = 0; sidx < maxst; ++sidx)
-      for (int type = IT_INIT; type <= IT_FINAL; ++type) {
+      for (int type = IT_INIT; type <= IT_HPSI_W; ++type) {
         const int item0 = (int)items.size();
         for (int i = 0; i < n_inst; ++i) {
             if (sidx >= inst_stage_count[i]) continue;
             const BatchStage &st = stages[b->insts[i].stage0 + sidx];
             if (st.type != type) continue;
-            const int nch = st.type == IT_FINAL ? 1 : b->insts[i].nchunks;
+            const int nch = st.type == IT_FINAL ? std::min(st.ntiles, 32) : b->insts[i].nchunks;
             for (int ch = 0; ch < nch; ++ch) {
                 const int t0 = (int)((int64_t)st.ntiles * ch / nch);
                 const int t1 = (int)((int64_t)st.ntiles * (ch + 1) / nch);
@@ -1793,7 +1804,6 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
         if ((int)items.size() > item0) b->groups.push_back({type, item0, (int)items.size() - item0});
       }
     b->nitems = (int)items.size();
-    b->persistent = env_int("SVQ_BATCH_PERSISTENT", 0) != 0;
     b->ops_inv = b->ops_fwd;
     hipStream_t s = b->stream;
     svq_batch bp = b.get();
@@ -1891,8 +1901,10 @@ svq_status sv_batch_run(svq_batch b, const double *const *theta, double *energie
         BHIPCHK(b, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
         BHIPCHK(b, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
         int grid = 0;
-        hipError_t le = hipSuccess;
-        if (b->persistent) {
+        // completion times are maxima over an instance's final blocks
+        hipError_t le = launch_fill_i32((int32_t *)b->t_done.p, 2 * b->n_inst, 0, cap);
+        if (le != hipSuccess) {
+        } else if (b->persistent) {
             le = launch_batch(b->args, (int32_t *)b->counters.p, b->nstages + 2, cap, &grid);
         } else {
             // the error flag stays zero: these launches never wait

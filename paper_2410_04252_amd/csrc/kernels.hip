@@ -1471,57 +1471,81 @@ static_assert((1 << HTPB) == 64, "one wave per tile");
 
 __device__ __forceinline__ double wave_sum_d(double v) { return wave_sum(v); }
 
-template <bool ADJ>
-__device__ __forceinline__ void gate_item(const BatchArgs &a, const BatchInst &N, const BatchPass &bp, uint32_t tile,
-                          float2 *lds, int chunk, bool first) {
+// One gate-pass tile of a batched instance: 2^KT amplitudes on 2^(KT-RB)
+// threads (one wave for KT = 10, four for KT = 12), as k_gate_pass does it.
+// The reverse pass adds each parametric op's block sum into the op's
+// (gate, chunk) slot; with several waves the per-wave sums are collected in
+// gacc (gsl holds the slot's gate) and summed in a fixed order.
+template <bool ADJ, int KT>
+__device__ __forceinline__ void gate_item(const BatchArgs &a, const BatchInst &N, const BatchPass &bp,
+                                          uint32_t tile, float2 *lds, double *gacc, int *gsl, int chunk,
+                                          bool first) {
     using R = float;
     using V = float2;
-    const uint32_t lane = threadIdx.x & 63u;
+    constexpr int RBT = gate_rb(KT);
+    constexpr int NRT = 1 << RBT;
+    constexpr int NW = 1 << (KT - RBT - 6);
+    constexpr int NWB = KT - RBT - 6;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     V *psi = a.arena + N.psi_off;
     V *lam = a.arena + N.lam_off;
     const OpDesc *ops = ADJ ? a.ops_inv : a.ops_fwd;
     const int np = bp.nphase;
     const PhaseDesc &P0 = a.phases[bp.phase0 + (ADJ ? np - 1 : 0)];
     const PhaseDesc &PL = a.phases[bp.phase0 + (ADJ ? 0 : np - 1)];
-    const uint64_t base = spread(tile, bp.tphys, K);
+    const uint64_t base = spread(tile, bp.tphys, KT);
     // instances have at most 26 qubits: in-tile byte offsets fit 32 bits
-    Regs<R, NR> v, w;
+    Regs<R, NRT> v, w;
     uint32_t sw;
-    RegMap<RB, K> mc;
+    RegMap<RBT, KT> mc;
     {
         uint32_t tp0;
-        thread_maps<0, K>(P0, bp.tphys, lane, 0u, tp0, sw);
+        thread_maps<NWB, KT>(P0, bp.tphys, lane, wave, tp0, sw);
         mc.init(P0, bp.tphys);
-        load_regs<V, R, NR, RB, K, true>(v, psi + base, tp0, mc);
-        if constexpr (ADJ) load_regs<V, R, NR, RB, K, true>(w, lam + base, tp0, mc);
+        load_regs<V, R, NRT, RBT, KT, true>(v, psi + base, tp0, mc);
+        if constexpr (ADJ) load_regs<V, R, NRT, RBT, KT, true>(w, lam + base, tp0, mc);
     }
+    int ng = 0;
+    auto flush = [&]() {
+        __syncthreads();
+        if ((int)threadIdx.x < ng) {
+            double sum = 0.0;
+#pragma unroll
+            for (int wv = 0; wv < NW; ++wv) sum += gacc[threadIdx.x * NW + wv];
+            double *slot = a.gpart + N.gpart_off + (size_t)gsl[threadIdx.x] * N.nchunks + chunk;
+            *slot = first ? sum : *slot + sum;   // this block owns the slot
+        }
+        ng = 0;
+        __syncthreads();
+    };
     for (int s = 0; s < np; ++s) {
         const PhaseDesc &Pc = a.phases[bp.phase0 + (ADJ ? np - 1 - s : s)];
         if (s > 0) {
-            __builtin_amdgcn_wave_barrier();
+            if constexpr (NW == 1) __builtin_amdgcn_wave_barrier();
+            else __syncthreads();
 #pragma unroll
-            for (int j = 0; j < NR; ++j) {
+            for (int j = 0; j < NRT; ++j) {
                 const uint32_t ad = sw ^ mc.slot(j);
                 lds[ad] = make_float2(v.re[j], v.im[j]);
-                if constexpr (ADJ) lds[(1 << K) + ad] = make_float2(w.re[j], w.im[j]);
+                if constexpr (ADJ) lds[(1 << KT) + ad] = make_float2(w.re[j], w.im[j]);
             }
             __syncthreads();
             uint32_t tpx;
-            thread_maps<0, K>(Pc, bp.tphys, lane, 0u, tpx, sw);
+            thread_maps<NWB, KT>(Pc, bp.tphys, lane, wave, tpx, sw);
             mc.init(Pc, bp.tphys);
 #pragma unroll
-            for (int j = 0; j < NR; ++j) {
+            for (int j = 0; j < NRT; ++j) {
                 const uint32_t ad = sw ^ mc.slot(j);
                 const V e = lds[ad];
                 v.re[j] = e.x;
                 v.im[j] = e.y;
                 if constexpr (ADJ) {
-                    const V f = lds[(1 << K) + ad];
+                    const V f = lds[(1 << KT) + ad];
                     w.re[j] = f.x;
                     w.im[j] = f.y;
                 }
             }
-            __syncthreads();
+            if constexpr (NW == 1) __syncthreads();
         }
         const int nop = Pc.nop;
         const int op0 = Pc.op0;
@@ -1529,39 +1553,57 @@ __device__ __forceinline__ void gate_item(const BatchArgs &a, const BatchInst &N
             const OpDesc &o = ops[op0 + (ADJ ? nop - 1 - q : q)];
             if constexpr (ADJ) {
                 if (o.gtype != GEN_NONE) {
-                    const double gv = wave_sum(op_gradient<R, NR, RB>(v, w, o));
-                    if (lane == 0) {
-                        double *slot = a.gpart + N.gpart_off + (size_t)o.gslot * N.nchunks + chunk;
-                        *slot = first ? gv : *slot + gv;   // this block owns the slot
+                    const double gv = wave_sum(op_gradient<R, NRT, RBT>(v, w, o));
+                    if constexpr (NW == 1) {
+                        if (lane == 0) {
+                            double *slot = a.gpart + N.gpart_off + (size_t)o.gslot * N.nchunks + chunk;
+                            *slot = first ? gv : *slot + gv;   // this block owns the slot
+                        }
+                    } else {
+                        if (lane == 0) gacc[ng * NW + wave] = gv;
+                        if (threadIdx.x == 0) gsl[ng] = o.gslot;
+                        if (++ng == kGradCap) flush();
                     }
                 }
-                apply_op<R, NR, RB>(w, o);
+                apply_op<R, NRT, RBT>(w, o);
             }
-            apply_op<R, NR, RB>(v, o);
+            apply_op<R, NRT, RBT>(v, o);
         }
     }
     uint32_t tpL, tsL;
-    thread_maps<0, K>(PL, bp.tphys, lane, 0u, tpL, tsL);
+    thread_maps<NWB, KT>(PL, bp.tphys, lane, wave, tpL, tsL);
     (void)tsL;
-    RegMap<RB, K> mL;
+    RegMap<RBT, KT> mL;
     mL.init(PL, bp.tphys);
-    store_regs<V, R, NR, RB, K, true>(v, psi + base, tpL, mL);
-    if constexpr (ADJ) store_regs<V, R, NR, RB, K, true>(w, lam + base, tpL, mL);
+    store_regs<V, R, NRT, RBT, KT, true>(v, psi + base, tpL, mL);
+    if constexpr (ADJ) {
+        store_regs<V, R, NRT, RBT, KT, true>(w, lam + base, tpL, mL);
+        if constexpr (NW > 1) {
+            if (ng) flush();
+        }
+    }
 }
 
-__device__ __forceinline__ void hpsi_item(const BatchArgs &a, const BatchInst &N, const BatchHPass &hp, int accumulate,
-                          uint32_t tile, float2 *lds) {
+// One H|psi> tile of a batched instance: 2^KH amplitudes on 2^(KH-4)
+// threads (one wave for KH = 10, four for KH = 12).
+template <int KH>
+__device__ __forceinline__ void hpsi_item(const BatchArgs &a, const BatchInst &N, const BatchHPass &hp,
+                                          int accumulate, uint32_t tile, float2 *lds) {
     using R = float;
     using V = float2;
+    constexpr int HTPB = hpsi_tpb(KH);
+    constexpr int HQ = KH - HTPB;
+    constexpr int HNQ = 1 << HQ;
+    static_assert(HQ == 4, "16 accumulators per thread");
     const float2 *psi = a.arena + N.psi_off;
     float2 *lam = a.arena + N.lam_off;
-    const uint64_t base = spread(tile, hp.tphys, K);
-    stage_tile<V, K, HTPB, int32_t>(lds, psi + base, hp.tphys);
+    const uint64_t base = spread(tile, hp.tphys, KH);
+    stage_tile<V, KH, HTPB, int32_t>(lds, psi + base, hp.tphys);
     __syncthreads();
     double lr[HNQ], li[HNQ];
 #pragma unroll
     for (int jj = 0; jj < HNQ; ++jj) lr[jj] = li[jj] = 0.0;
-    const uint32_t tid = threadIdx.x & 63u;
+    const uint32_t tid = threadIdx.x;
     for (int gi = 0; gi < hp.ngroups; ++gi) {
         const HpsiGroup &G = a.hgroups[hp.group0 + gi];
         const uint32_t sthr = tid ^ G.xt;
@@ -1639,14 +1681,20 @@ __device__ __forceinline__ double dot_tile(const BatchArgs &a, const BatchInst &
     return acc;
 }
 
-__device__ __forceinline__ void final_item(const BatchArgs &a, const BatchInst &N, int inst) {
+// Final sums of one instance, slots [s0, s0 + ns): slot p < ntheta is
+// dE/dtheta_p (its gates' chunk partials), slot ntheta the energy (the
+// chunk partials of <psi|H psi>).  Several blocks share an instance's slots.
+__device__ __forceinline__ void final_item(const BatchArgs &a, const BatchInst &N, int inst, int s0,
+                                           int ns) {
     const uint32_t lane = threadIdx.x & 63u;
-    double e = 0.0;
-    for (int t = lane; t < N.nchunks; t += 64) e += a.epart[N.epart_off + t];
-    e = wave_sum(e);
-    if (lane == 0) a.energies[inst] = e;
-    for (int p = 0; p < N.ntheta; ++p) {
+    for (int p = s0; p < s0 + ns; ++p) {
         double g = 0.0;
+        if (p == N.ntheta) {
+            for (int t = lane; t < N.nchunks; t += 64) g += a.epart[N.epart_off + t];
+            g = wave_sum(g);
+            if (lane == 0) a.energies[inst] = g;
+            continue;
+        }
         const int e0 = a.pptr[N.pptr_off + p], e1 = a.pptr[N.pptr_off + p + 1];
         for (int q = e0; q < e1; ++q) {
             const double *src = a.gpart + N.gpart_off + (size_t)a.pgate[q] * N.nchunks;
@@ -1655,6 +1703,12 @@ __device__ __forceinline__ void final_item(const BatchArgs &a, const BatchInst &
         g = wave_sum(g);
         if (lane == 0) a.grads[N.grad_off + p] = g;
     }
+}
+
+// Completion time of an instance: the latest of its final blocks.
+__device__ __forceinline__ void stamp_done(const BatchArgs &a, int inst) {
+    __hip_atomic_fetch_max(a.t_done + inst, (uint64_t)__builtin_amdgcn_s_memrealtime(), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace batch
@@ -1705,11 +1759,11 @@ __global__ __launch_bounds__(64) void k_batch(const BatchArgs a) {
             const uint32_t tile = (uint32_t)(I.tile0 + k);
             switch (S.type) {
             case IT_INIT: batch::init_item(a, N, tile); break;
-            case IT_FWD: batch::gate_item<false>(a, N, a.passes[S.desc], tile, lds, I.chunk, k == 0); break;
-            case IT_HPSI: batch::hpsi_item(a, N, a.hpasses[S.desc], S.accumulate, tile, lds); break;
+            case IT_FWD: batch::gate_item<false, kBatchK>(a, N, a.passes[S.desc], tile, lds, nullptr, nullptr, I.chunk, k == 0); break;
+            case IT_HPSI: batch::hpsi_item<kBatchK>(a, N, a.hpasses[S.desc], S.accumulate, tile, lds); break;
             case IT_DOT: dacc += batch::dot_tile(a, N, tile); break;
-            case IT_ADJ: batch::gate_item<true>(a, N, a.passes[S.desc], tile, lds, I.chunk, k == 0); break;
-            default: batch::final_item(a, N, I.inst); break;
+            case IT_ADJ: batch::gate_item<true, kBatchK>(a, N, a.passes[S.desc], tile, lds, nullptr, nullptr, I.chunk, k == 0); break;
+            default: batch::final_item(a, N, I.inst, I.tile0, I.ntile); k = I.ntile; break;
             }
         }
         if (S.type == IT_DOT) {
@@ -1718,7 +1772,7 @@ __global__ __launch_bounds__(64) void k_batch(const BatchArgs a) {
         }
         if (lane == 0) {
             __hip_atomic_fetch_add(a.done + sidx, I.ntile, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            if (S.type == IT_FINAL) a.t_done[I.inst] = __builtin_amdgcn_s_memrealtime();
+            if (S.type == IT_FINAL) batch::stamp_done(a, I.inst);
         }
     }
 }
@@ -1729,9 +1783,16 @@ __global__ __launch_bounds__(64) void k_batch(const BatchArgs a) {
 // and each item type gets a kernel of its own (registers and LDS sized for
 // that type alone rather than for the largest of all types).
 template <int TYPE>
-__global__ __launch_bounds__(64) void k_batch_stage(const BatchArgs a, int item0) {
-    constexpr int NLDS = TYPE == IT_ADJ ? (2 << kBatchK) : (TYPE == IT_FWD || TYPE == IT_HPSI) ? (1 << kBatchK) : 1;
+__global__ __launch_bounds__((TYPE == IT_FWD_W || TYPE == IT_ADJ_W || TYPE == IT_HPSI_W) ? 256 : 64) void
+k_batch_stage(const BatchArgs a, int item0) {
+    constexpr int NLDS = TYPE == IT_ADJ_W ? (2 << kBatchKWide)
+                       : (TYPE == IT_FWD_W || TYPE == IT_HPSI_W) ? (1 << kBatchKWide)
+                       : TYPE == IT_ADJ ? (2 << kBatchK)
+                       : (TYPE == IT_FWD || TYPE == IT_HPSI) ? (1 << kBatchK) : 1;
+    constexpr int NGW = TYPE == IT_ADJ_W ? kGradCap * 4 : 1;
     __shared__ float2 lds[NLDS];
+    __shared__ double gacc[NGW];
+    __shared__ int gsl[TYPE == IT_ADJ_W ? kGradCap : 1];
     const uint32_t lane = threadIdx.x & 63u;
     const BatchItem I = a.items[item0 + (int)blockIdx.x];
     const BatchInst &N = a.insts[I.inst];
@@ -1743,18 +1804,21 @@ __global__ __launch_bounds__(64) void k_batch_stage(const BatchArgs a, int item0
     for (int k = 0; k < I.ntile; ++k) {
         const uint32_t tile = (uint32_t)(I.tile0 + k);
         if constexpr (TYPE == IT_INIT) batch::init_item(a, N, tile);
-        else if constexpr (TYPE == IT_FWD) batch::gate_item<false>(a, N, a.passes[S.desc], tile, lds, I.chunk, k == 0);
-        else if constexpr (TYPE == IT_HPSI) batch::hpsi_item(a, N, a.hpasses[S.desc], S.accumulate, tile, lds);
+        else if constexpr (TYPE == IT_FWD) batch::gate_item<false, kBatchK>(a, N, a.passes[S.desc], tile, lds, gacc, gsl, I.chunk, k == 0);
+        else if constexpr (TYPE == IT_FWD_W) batch::gate_item<false, kBatchKWide>(a, N, a.passes[S.desc], tile, lds, gacc, gsl, I.chunk, k == 0);
+        else if constexpr (TYPE == IT_ADJ_W) batch::gate_item<true, kBatchKWide>(a, N, a.passes[S.desc], tile, lds, gacc, gsl, I.chunk, k == 0);
+        else if constexpr (TYPE == IT_HPSI) batch::hpsi_item<kBatchK>(a, N, a.hpasses[S.desc], S.accumulate, tile, lds);
+        else if constexpr (TYPE == IT_HPSI_W) batch::hpsi_item<kBatchKWide>(a, N, a.hpasses[S.desc], S.accumulate, tile, lds);
         else if constexpr (TYPE == IT_DOT) dacc += batch::dot_tile(a, N, tile);
-        else if constexpr (TYPE == IT_ADJ) batch::gate_item<true>(a, N, a.passes[S.desc], tile, lds, I.chunk, k == 0);
+        else if constexpr (TYPE == IT_ADJ) batch::gate_item<true, kBatchK>(a, N, a.passes[S.desc], tile, lds, gacc, gsl, I.chunk, k == 0);
     }
     if constexpr (TYPE == IT_DOT) {
         dacc = wave_sum(dacc);
         if (lane == 0) a.epart[N.epart_off + I.chunk] = dacc;
     }
     if constexpr (TYPE == IT_FINAL) {
-        batch::final_item(a, N, I.inst);
-        if (lane == 0) a.t_done[I.inst] = __builtin_amdgcn_s_memrealtime();
+        batch::final_item(a, N, I.inst, I.tile0, I.ntile);
+        if (lane == 0) batch::stamp_done(a, I.inst);
     }
 }
 
@@ -1790,6 +1854,9 @@ hipError_t launch_batch_stage(const BatchArgs &a, int type, int item0, int nitem
     case IT_DOT: hipLaunchKernelGGL(k_batch_stage<IT_DOT>, dim3(nitem), dim3(64), 0, s, a, item0); break;
     case IT_ADJ: hipLaunchKernelGGL(k_batch_stage<IT_ADJ>, dim3(nitem), dim3(64), 0, s, a, item0); break;
     case IT_FINAL: hipLaunchKernelGGL(k_batch_stage<IT_FINAL>, dim3(nitem), dim3(64), 0, s, a, item0); break;
+    case IT_FWD_W: hipLaunchKernelGGL(k_batch_stage<IT_FWD_W>, dim3(nitem), dim3(256), 0, s, a, item0); break;
+    case IT_ADJ_W: hipLaunchKernelGGL(k_batch_stage<IT_ADJ_W>, dim3(nitem), dim3(256), 0, s, a, item0); break;
+    case IT_HPSI_W: hipLaunchKernelGGL(k_batch_stage<IT_HPSI_W>, dim3(nitem), dim3(256), 0, s, a, item0); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

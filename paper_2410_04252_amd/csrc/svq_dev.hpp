@@ -181,7 +181,9 @@ namespace svq {
 // one queue.  All descriptor fields are 32-bit (scalar loads).
 // ---------------------------------------------------------------------------
 
-constexpr int kBatchK = 10;          // tile bits of every batched stage
+constexpr int kBatchK = 10;          // tile bits of the batched stages
+constexpr int kBatchKWide = 12;      // tile bits of the gate passes of large instances
+constexpr int kBatchWideN = 16;      // instances of at least this many qubits use them
 constexpr int kBatchSpinLimit = 1 << 24;
 
 enum ItemType : int32_t {
@@ -191,6 +193,9 @@ enum ItemType : int32_t {
     IT_DOT = 3,     // tile partial of Re <psi|lambda>
     IT_ADJ = 4,     // reverse adjoint pass on psi and lambda
     IT_FINAL = 5,   // energy and gradient of the instance
+    IT_FWD_W = 6,   // forward gate pass on 2^12-amplitude tiles (4-wave blocks)
+    IT_ADJ_W = 7,   // reverse adjoint pass on 2^12-amplitude tiles
+    IT_HPSI_W = 8,  // H|psi> pass on 2^12-amplitude tiles
 };
 
 // One item: tiles [tile0, tile0 + ntile) of one stage, handled by one block,
