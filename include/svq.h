@@ -323,9 +323,10 @@ svq_status sv_tune_circuit(svq_state st, const svq_gate *gates, int m, const dou
                            int n_theta, svq_sched sched, int *k_out, int *c_out, double *ms_out);
 svq_status sv_tune_paulis(svq_state st, const svq_pauli *terms, int n_terms, int *k_out,
                           int *c_out, double *ms_out);
-/* Batch: tries items per stage (chunks) and low bits; arguments as
- * sv_batch_create plus the angles; the winner is used by later
- * sv_batch_create calls with low_bits = 0. */
+/* Batch: tries items per stage (chunks), low bits, and the size class from
+ * which instances run their gate and H|psi> passes on 2^12-amplitude tiles
+ * (12, 16, 20 qubits, or none); arguments as sv_batch_create plus the angles;
+ * the winner is used by later sv_batch_create calls with low_bits = 0. */
 svq_status sv_batch_tune(int n_inst, const int32_t *n_qubits, const svq_gate *const *gates,
                          const int32_t *m, const int32_t *n_theta, const svq_pauli *const *terms,
                          const int32_t *n_terms, const uint64_t *psi0, const double *const *theta,

@@ -1645,7 +1645,9 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
     // Large instances run their gate passes on 2^12-amplitude tiles with
     // 4-wave blocks (fewer passes, the single-state pass's layout); the
     // persistent form keeps every stage on 2^10 tiles.
-    const int wide_n = env_int("SVQ_BATCH_WIDE_N", kBatchWideN);
+    TuneVal tw{kBatchWideN, 0, 0.0};
+    (void)tuned(3, 0, 0, 0, tw);
+    const int wide_n = env_int("SVQ_BATCH_WIDE_N", tw.k);
     for (int i = 0; i < n_inst; ++i) {
         const int n = n_qubits[i];
         const bool wide = !b->persistent && n >= wide_n && n >= kBatchKWide;
@@ -2163,11 +2165,17 @@ svq_status sv_batch_tune(int n_inst, const int32_t *n_qubits, const svq_gate *co
     for (int i = 0; i < n_inst; ++i) total += n_theta ? n_theta[i] : 0;
     std::vector<double> e(n_inst), g(std::max(1, total));
     TuneVal best{0, 0, 1e300};
-    const int chunk_c[] = {64, 256, 1024, 4096};
-    const int low_c[] = {3, 4, 5};
+    // items per stage, low bits, and the size class from which instances run
+    // their gate and H|psi> passes on 2^12 tiles (27: none)
+    const int chunk_c[] = {256, 1024};
+    const int low_c[] = {3, 4};
+    const int wide_c[] = {12, 16, 20, 27};
+    TuneVal best_w{kBatchWideN, 0, 1e300};
     for (int ch : chunk_c)
-        for (int c : low_c) {
+        for (int c : low_c)
+          for (int wn : wide_c) {
             set_tuned(2, 0, 0, 0, {ch, c, 0.0});
+            set_tuned(3, 0, 0, 0, {wn, 0, 0.0});
             svq_batch b = nullptr;
             svq_status s = sv_batch_create(n_inst, n_qubits, gates, m, n_theta, terms, n_terms, psi0,
                                            0, stream, &b);
@@ -2179,9 +2187,13 @@ svq_status sv_batch_tune(int n_inst, const int32_t *n_qubits, const svq_gate *co
             (void)sv_batch_destroy(b);
             if (s) return s;
             const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-            if (ms < best.ms) best = {ch, c, ms};
-        }
+            if (ms < best.ms) {
+                best = {ch, c, ms};
+                best_w = {wn, 0, ms};
+            }
+          }
     set_tuned(2, 0, 0, 0, best);
+    set_tuned(3, 0, 0, 0, best_w);
     if (chunks_out) *chunks_out = best.k;
     if (low_bits_out) *low_bits_out = best.c;
     if (ms_out) *ms_out = best.ms;

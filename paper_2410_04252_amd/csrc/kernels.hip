@@ -433,7 +433,17 @@ __device__ __forceinline__ void load_regs(Regs<R, NR> &v, const V *__restrict__ 
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         V e;
-        if constexpr (OFF32) {
+        if constexpr (OFF32 && sizeof(V) == 16) {
+            // 16-byte amplitudes stream with non-temporal accesses (measured
+            // faster for complex128; for 8-byte amplitudes the non-temporal
+            // stores are several times slower, so complex64 keeps the plain
+            // ones)
+            const uint32_t off = (tp + m.phys(j)) * (uint32_t)sizeof(V);
+            typedef R r2_t __attribute__((ext_vector_type(2)));
+            const r2_t t2 = __builtin_nontemporal_load((const r2_t *)((const char *)src + off));
+            e.x = t2.x;
+            e.y = t2.y;
+        } else if constexpr (OFF32) {
             const uint32_t off = (tp + m.phys(j)) * (uint32_t)sizeof(V);
             e = *(const V *)((const char *)src + off);
         } else {
@@ -452,7 +462,14 @@ __device__ __forceinline__ void store_regs(const Regs<R, NR> &v, V *__restrict__
         V e;
         e.x = v.re[j];
         e.y = v.im[j];
-        if constexpr (OFF32) {
+        if constexpr (OFF32 && sizeof(V) == 16) {
+            const uint32_t off = (tp + m.phys(j)) * (uint32_t)sizeof(V);
+            typedef R r2_t __attribute__((ext_vector_type(2)));
+            r2_t t2;
+            t2.x = e.x;
+            t2.y = e.y;
+            __builtin_nontemporal_store(t2, (r2_t *)((char *)dst + off));
+        } else if constexpr (OFF32) {
             const uint32_t off = (tp + m.phys(j)) * (uint32_t)sizeof(V);
             *(V *)((char *)dst + off) = e;
         } else {

@@ -48,7 +48,7 @@ def test_tuned_batch_matches_oracle(P):
     b = P.Batch(inst)
     ch, lb, ms = b.tune()
     b.close()
-    assert ch in (64, 256, 1024, 4096) and lb in (3, 4, 5) and ms > 0
+    assert ch in (256, 1024) and lb in (3, 4) and ms > 0
     b = P.Batch(inst)                  # built with the tuned values
     e, grads, _ = b.run()
     for i, (c, h) in enumerate(inst):
