@@ -1571,7 +1571,9 @@ struct svq_batch_s {
     int nitems = 0, nstages = 0, total_theta = 0;
     double bytes_per_run = 0;              // algorithmic HBM bytes of one run
     bool persistent = false;               // one persistent launch, else level-synchronous
-    std::vector<std::array<int, 3>> groups;   // level-synchronous launches: type, item0, count
+    // level-synchronous launches: type, item0, count, size class (1: the
+    // instances whose gate passes use 2^12 tiles)
+    std::vector<std::array<int, 4>> groups;
     DevBuf arena, items, stages, dinsts, passes, hpasses, phases, d_ops_fwd, d_ops_inv, hgroups,
         hterms, pptr, pgate, epart, gpart, energies, grads, counters, t_done, t_start;
     OpDesc *h_ops_fwd = nullptr, *h_ops_inv = nullptr;   // pinned staging
@@ -1641,6 +1643,7 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
     int64_t arena_elems = 0;
     int epart_total = 0, gpart_total = 0;
     std::vector<int> inst_stage_count(n_inst);
+    std::vector<int> inst_wide(n_inst, 0);
     b->persistent = env_int("SVQ_BATCH_PERSISTENT", 0) != 0;
     // Large instances run their gate passes on 2^12-amplitude tiles with
     // 4-wave blocks (fewer passes, the single-state pass's layout); the
@@ -1652,6 +1655,7 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
         const int n = n_qubits[i];
         const bool wide = !b->persistent && n >= wide_n && n >= kBatchKWide;
         const int KG = wide ? kBatchKWide : K;
+        inst_wide[i] = wide;
         if (n < K || n > 26) return fail(SVQ_EINVAL, "batch instances need 10 <= n <= 26");
         if (m[i] < 0 || n_theta[i] < 0 || n_terms[i] < 1) return fail(SVQ_EINVAL, "bad instance sizes");
         if (psi0[i] >> n) return fail(SVQ_EINVAL, "psi0 index >= 2^n");
@@ -1783,10 +1787,11 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
     // item's predecessor earlier in the queue, the level-synchronous launches
     // one contiguous range per (level, type).
     for (int sidx = 0; sidx < maxst; ++sidx)
-      for (int type = IT_INIT; type <= IT_HPSI_W; ++type) {
+      for (int type = IT_INIT; type <= IT_HPSI_W; ++type)
+       for (int cls = 0; cls < 2; ++cls) {
         const int item0 = (int)items.size();
         for (int i = 0; i < n_inst; ++i) {
-            if (sidx >= inst_stage_count[i]) continue;
+            if (sidx >= inst_stage_count[i] || inst_wide[i] != cls) continue;
             const BatchStage &st = stages[b->insts[i].stage0 + sidx];
             if (st.type != type) continue;
             const int nch = st.type == IT_FINAL ? std::min(st.ntiles, 32) : b->insts[i].nchunks;
@@ -1803,8 +1808,8 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
                 items.push_back(it);
             }
         }
-        if ((int)items.size() > item0) b->groups.push_back({type, item0, (int)items.size() - item0});
-      }
+        if ((int)items.size() > item0) b->groups.push_back({type, item0, (int)items.size() - item0, cls});
+       }
     b->nitems = (int)items.size();
     b->ops_inv = b->ops_fwd;
     hipStream_t s = b->stream;
@@ -1908,13 +1913,34 @@ svq_status sv_batch_run(svq_batch b, const double *const *theta, double *energie
         if (le != hipSuccess) {
         } else if (b->persistent) {
             le = launch_batch(b->args, (int32_t *)b->counters.p, b->nstages + 2, cap, &grid);
-        } else {
+        }
+        // The two size classes share no data: the small instances' launches
+        // go on a branch of their own (forked and joined with events), so
+        // they are not queued behind the large instances' launches.
+        hipStream_t side = nullptr;
+        hipEvent_t fork = nullptr, join = nullptr;
+        if (le == hipSuccess && !b->persistent) {
             // the error flag stays zero: these launches never wait
             le = launch_fill_i32((int32_t *)b->counters.p, b->nstages + 2, 0, cap);
-            for (size_t gi = 0; gi < b->groups.size() && le == hipSuccess; ++gi)
-                le = launch_batch_stage(b->args, b->groups[gi][0], b->groups[gi][1], b->groups[gi][2], cap);
+            bool cls_used[2] = {false, false};
+            for (const auto &gr : b->groups) cls_used[gr[3]] = true;
+            const bool branch = cls_used[0] && cls_used[1];
+            if (branch && le == hipSuccess) le = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+            if (branch && le == hipSuccess) le = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+            if (branch && le == hipSuccess) le = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+            if (branch && le == hipSuccess) le = hipEventRecord(fork, cap);
+            if (branch && le == hipSuccess) le = hipStreamWaitEvent(side, fork, 0);
+            for (size_t gi = 0; gi < b->groups.size() && le == hipSuccess; ++gi) {
+                const auto &gr = b->groups[gi];
+                le = launch_batch_stage(b->args, gr[0], gr[1], gr[2], (branch && gr[3] == 0) ? side : cap);
+            }
+            if (branch && le == hipSuccess) le = hipEventRecord(join, side);
+            if (branch && le == hipSuccess) le = hipStreamWaitEvent(cap, join, 0);
         }
         hipError_t ce = hipStreamEndCapture(cap, &b->graph);
+        if (side) (void)hipStreamDestroy(side);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
         (void)hipStreamDestroy(cap);
         BHIPCHK(b, le, "launch batch");
         BHIPCHK(b, ce, "end capture");
