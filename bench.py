@@ -61,6 +61,21 @@ def counted_traffic(path, kernel, workload):
     return tf.get("bytes_per_launch")
 
 
+def pass_ceiling(P, st, gate_pass_ms_per_run):
+    """Every gate pass of the handle's last circuit plan run again without its
+    gates (sv_pass_ceiling: the same tile bits and phase count, so the same
+    loads, stores and LDS transposes): the data movement alone, per run."""
+    plan = st.plan_dump()
+    tot, npass = 0.0, 0
+    for s in plan.get("steps", []):
+        if s["type"] != "gate_pass":
+            continue
+        tot += P.sv_pass_ceiling(st.h, s["tile_bits"], s["phases"], reps=3)
+        npass += 1
+    return dict(empty_pass_ms_per_run=round(tot, 3), gate_pass_ms_per_run=round(gate_pass_ms_per_run, 3),
+                passes=npass, frac_of_ceiling=round(tot / gate_pass_ms_per_run, 4) if gate_pass_ms_per_run else None)
+
+
 def measure_main(P, W, torch, args):
     cfg = W.config(args.workload)
     circ, ham, g = cfg["circuit"], cfg["ham"], cfg["g"]
@@ -127,6 +142,14 @@ def measure_main(P, W, torch, args):
     gp_bytes = 2.0 * S                     # one read + one write of the state per launch
     achieved = gp_bytes / (gp_avg_ms * 1e-3) / 1e9
     evc_roof = evc_roofline(n, nt, t_ev / args.steps, dtype)
+    # the same passes without their gates (after the timed region)
+    ceiling = None
+    if not args.no_ceiling:
+        P.sv_set_basis(h, circ.psi0_index)
+        P.sv_apply_circuit(h, gates_c, m, theta, len(theta), P.LAZY, args.tile_k)
+        ceiling = pass_ceiling(P, st, t_gp / args.steps)
+        log(f"[bench] the {ceiling['passes']} gate passes without gates: {ceiling['empty_pass_ms_per_run']:.2f} ms "
+            f"per run against {ceiling['gate_pass_ms_per_run']:.2f} ms with them")
     if args.no_eager:
         st.close()
         return dict(
@@ -143,7 +166,8 @@ def measure_main(P, W, torch, args):
             roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
                           kernel="k_gate_pass<%s,%d,4,false,true>" % (ELEM[dtype], s1.tile_k or 12),
-                          bytes_per_launch=gp_bytes, launches=n_gp, avg_ms=gp_avg_ms))
+                          bytes_per_launch=gp_bytes, launches=n_gp, avg_ms=gp_avg_ms,
+                          ceiling=ceiling))
     # eager comparison (one run, not part of the timed steps)
     P.sv_set_basis(h, circ.psi0_index)
     torch.cuda.synchronize()
@@ -190,7 +214,7 @@ def measure_main(P, W, torch, args):
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
                       kernel="k_gate_pass<%s,%d,4,false,true>" % (ELEM[dtype], s1.tile_k or 12),
-                      bytes_per_launch=gp_bytes, launches=n_gp, avg_ms=gp_avg_ms),
+                      bytes_per_launch=gp_bytes, launches=n_gp, avg_ms=gp_avg_ms, ceiling=ceiling),
     )
     return out
 
@@ -315,6 +339,11 @@ def measure_c128(P, W, torch, args):
     n_ev, t_ev = P.sv_profile_read(h, P.PROF_EVC)
     n_qr, t_qr = P.sv_profile_read(h, P.PROF_QR)
     P.sv_profile(h, 0)
+    ceiling = None
+    if not args.no_ceiling:
+        P.sv_set_basis(h, circ.psi0_index)
+        P.sv_apply_circuit(h, gc, m, circ.theta, len(circ.theta), P.LAZY, 0)
+        ceiling = pass_ceiling(P, st, t_gp / reps)
     st.close()
     S = (1 << n) * 16
     gp_avg = t_gp / max(1, n_gp)
@@ -332,7 +361,8 @@ def measure_c128(P, W, torch, args):
                 energy=e,
                 roofline=dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                               frac=round(gbs / HBM_PEAK_GBS, 4), traffic=traffic,
-                              kernel=kname, bytes_per_launch=2 * S, launches=n_gp, avg_ms=gp_avg),
+                              kernel=kname, bytes_per_launch=2 * S, launches=n_gp, avg_ms=gp_avg,
+                              ceiling=ceiling),
                 evc_roofline=evc_roofline(n, nt, t_ev / reps, "c128"))
 
 
@@ -718,6 +748,8 @@ def main():
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the hea12 / fabric28 / fabric32 configuration legs")
     ap.add_argument("--no-fabric32", action="store_true", help="skip the 32-qubit legs")
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip re-running the gate passes without gates (profiling runs)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--tune", action="store_true",
                     help="run the measured tuner on the workload before timing")

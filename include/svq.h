@@ -376,6 +376,18 @@ svq_status sv_qr_cost(int n, int n_local, int n_intra, const uint64_t *targets, 
                       int fill_highest, double w_intra, double w_inter, int32_t *n_intra_out,
                       int32_t *n_inter_out, double *cost_out);
 
+/* The data movement of one gate pass alone: the gate-pass kernel run over
+ * the handle's state with no gates, on tiles of the k local physical bit
+ * positions tile_bits[0..k) (ascending; a real pass has the c lowest ones
+ * among them), with nphase phases whose register bits alternate so that
+ * each of the nphase - 1 phase changes is a full LDS transpose.  It reads
+ * and writes every amplitude once and leaves the state unchanged.  One warm
+ * launch, then reps timed launches (HIP events on the handle's stream);
+ * *ms_out receives the average per launch.  The ceiling against which the
+ * gate pass's HBM fraction is judged.  Errors: EINVAL, EHIP. */
+svq_status sv_pass_ceiling(svq_state st, const int32_t *tile_bits, int k, int nphase, int reps,
+                           double *ms_out);
+
 /* A plain streaming copy of device memory (16-byte accesses, asynchronous on
  * the stream): the reference against which pass bandwidths and the HBM
  * traffic counters are calibrated.  bytes must be a multiple of 16; the

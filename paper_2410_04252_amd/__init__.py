@@ -55,7 +55,7 @@ EXPORTS = ("sv_create", "sv_destroy", "sv_set_basis", "sv_set_amplitudes", "sv_g
            "sv_expectation", "sv_expectation_qsu", "sv_apply_hamiltonian", "sv_grad", "sv_param_shift_grad", "sv_plan_circuit",
            "sv_plan_circuit_json", "sv_plan_paulis", "sv_plan_ops", "sv_qr_cost", "sv_tune_circuit", "sv_tune_paulis",
            "sv_batch_tune", "sv_tune_save", "sv_tune_load", "sv_profile", "sv_profile_read", "sv_batch_create", "sv_batch_run",
-           "sv_batch_destroy", "sv_batch_info", "sv_device_copy", "sv_last_error")
+           "sv_batch_destroy", "sv_batch_info", "sv_device_copy", "sv_pass_ceiling", "sv_last_error")
 
 
 def _load():
@@ -118,6 +118,7 @@ def _load():
     L.sv_qr_cost.argtypes = [c_int, c_int, c_int, POINTER(c_uint64), c_int, c_int, c_int, c_double,
                              c_double, POINTER(c_int32), POINTER(c_int32), POINTER(c_double)]
     L.sv_batch_info.argtypes = [vp, POINTER(c_double), POINTER(c_int32), POINTER(c_int32)]
+    L.sv_pass_ceiling.argtypes = [vp, POINTER(c_int32), c_int, c_int, c_int, POINTER(c_double)]
     L.sv_profile.argtypes = [vp, c_int]
     L.sv_profile_read.argtypes = [vp, c_int, POINTER(c_int), POINTER(c_double)]
     L.sv_device_copy.argtypes = [vp, vp, c_size_t, vp]
@@ -390,6 +391,14 @@ def sv_qr_cost(n, n_local, n_intra, targets, method, w_intra=1.0, w_inter=10.0, 
     _check(lib.sv_qr_cost(n, n_local, n_intra, tm, m, method, int(fill_highest), w_intra, w_inter,
                           byref(ni), byref(ne), byref(cost)))
     return ni.value, ne.value, cost.value
+
+
+def sv_pass_ceiling(h, tile_bits, nphase, reps=5):
+    """Average ms of one gate pass without gates over the given tile bits."""
+    tb = (c_int32 * len(tile_bits))(*tile_bits)
+    ms = c_double()
+    _check(lib.sv_pass_ceiling(h, tb, len(tile_bits), nphase, reps, byref(ms)))
+    return ms.value
 
 
 def sv_plan_paulis(n, g, ham, sched, tile_k=0):

@@ -865,6 +865,50 @@ svq_status sv_device_copy(const void *src, void *dst, size_t bytes, void *stream
     return SVQ_OK;
 }
 
+svq_status sv_pass_ceiling(svq_state st, const int32_t *tile_bits, int k, int nphase, int reps,
+                           double *ms_out) {
+    if (!st) return fail(SVQ_EINVAL, "null handle");
+    if (st->poisoned) return fail(SVQ_EPOISONED, "handle poisoned by an earlier failure");
+    if (!tile_bits || !ms_out || reps < 1 || reps > 1000) return fail(SVQ_EINVAL, "bad arguments");
+    if (k < 10 || k > 13 || k > st->n - st->g) return fail(SVQ_EINVAL, "k must be in [10, 13] and at most n - g");
+    std::vector<int> tb(tile_bits, tile_bits + k);
+    for (int j = 0; j < k; ++j)
+        if (tb[j] >= st->n - st->g) return fail(SVQ_EINVAL, "tile bits must be local positions");
+    CircuitPlan P;
+    const std::string err = plan_empty_pass(st->n, k, gate_rb(k), tb.data(), nphase, P);
+    if (!err.empty()) return fail(SVQ_EINVAL, err);
+    HIPCHK(st, hipSetDevice(st->device), "hipSetDevice");
+    DevBuf ph;
+    HIPCHK(st, ph.ensure(sizeof(PhaseDesc) * P.phases.size()), "alloc phases");
+    HIPCHK(st, hipMemcpyAsync(ph.p, P.phases.data(), sizeof(PhaseDesc) * P.phases.size(),
+                              hipMemcpyHostToDevice, st->stream),
+           "upload phases");
+    const PassArgs &a = P.passes[0];
+    const OpDesc *no_ops = (const OpDesc *)ph.p;   // never read: every phase has nop = 0
+    hipEvent_t e0, e1;
+    HIPCHK(st, hipEventCreate(&e0), "event");
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        HIPCHK(st, he, "event");
+    }
+    he = launch_gate_pass(st->dbl(), k, P.rb, false, st->buf, nullptr, a, (const PhaseDesc *)ph.p, no_ops,
+                          nullptr, a.nblocks, st->stream);   // warm
+    if (he == hipSuccess) he = hipEventRecord(e0, st->stream);
+    for (int r = 0; r < reps && he == hipSuccess; ++r)
+        he = launch_gate_pass(st->dbl(), k, P.rb, false, st->buf, nullptr, a, (const PhaseDesc *)ph.p,
+                              no_ops, nullptr, a.nblocks, st->stream);
+    if (he == hipSuccess) he = hipEventRecord(e1, st->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(st, he, "pass ceiling");
+    *ms_out = (double)ms / reps;
+    return SVQ_OK;
+}
+
 svq_status sv_plan_dump(svq_state st, char *json_buf, size_t cap, size_t *len_out) {
     if (!st) return fail(SVQ_EINVAL, "null handle");
     const std::string empty = "{}";

@@ -1020,6 +1020,47 @@ static void choose_swizzle(int k, CircuitPlan &P, PassArgs &pa, const int *ld, i
     }
 }
 
+std::string plan_empty_pass(int n, int k, int rb, const int *tile_bits, int nphase, CircuitPlan &out) {
+    if (k < rb + 6 || k > 16 || k > n || nphase < 1 || nphase > 64) return "bad pass shape";
+    for (int j = 0; j < k; ++j)
+        if (tile_bits[j] < 0 || tile_bits[j] >= n || (j && tile_bits[j] <= tile_bits[j - 1]))
+            return "tile bits must be ascending positions below n";
+    out = CircuitPlan();
+    out.n = n;
+    out.g = 0;
+    out.k = k;
+    out.rb = rb;
+    PassArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    for (int j = 0; j < k; ++j) pa.tphys[j] = pa.tphys_out[j] = tile_bits[j];
+    pa.nblocks = 1 << (n - k);
+    pa.phase0 = 0;
+    pa.nphase = nphase;
+    int lows[6];
+    for (int i = 0; i < 6; ++i) lows[i] = i;
+    const uint32_t top = ((1u << rb) - 1u) << (k - rb);
+    const uint32_t mid = ((1u << rb) - 1u) << 6;
+    for (int ph = 0; ph < nphase; ++ph) {
+        PhaseDesc D;
+        std::memset(&D, 0, sizeof(D));
+        const uint32_t regs = (ph & 1) ? mid : top;
+        set_regs(regs, rb, D);
+        if (ph == 0 || ph == nphase - 1) io_lanes(k, regs, lows, std::min(k - rb, 6), D);
+        else assign_lanes(k, regs, D);
+        D.op0 = 0;
+        D.nop = 0;
+        out.phases.push_back(D);
+    }
+    out.n_phases_total = nphase;
+    choose_swizzle(k, out, pa, lows, 6, lows, 6);
+    out.passes.push_back(pa);
+    Step s;
+    s.type = 1;
+    s.idx = 0;
+    out.steps.push_back(s);
+    return "";
+}
+
 std::string plan_circuit(int n, int g, const std::vector<GateN> &gates, svq_sched sched, int k,
                          int rb, int c, const std::vector<int> &pos0, CircuitPlan &out,
                          bool relayout) {

@@ -101,6 +101,13 @@ struct CircuitPlan {
 // relayout: passes may store their tile with its bit positions permuted
 // (PassArgs::tphys_out), so that the next pass's qubits sit on the c lowest
 // positions; otherwise every tile takes the c lowest positions as they are.
+// One gate pass without gates over the tile bits tile_bits[0..k) (ascending
+// physical positions): nphase phases whose registers alternate between the
+// tile's top rb bits and the rb bits above the six lowest, so that every
+// phase change is a full LDS transpose.  The load phase has its lanes on the
+// six lowest tile bits.  Used to measure the data movement of a pass alone.
+std::string plan_empty_pass(int n, int k, int rb, const int *tile_bits, int nphase, CircuitPlan &out);
+
 std::string plan_circuit(int n, int g, const std::vector<GateN> &gates, svq_sched sched, int k,
                          int rb, int c, const std::vector<int> &pos0, CircuitPlan &out,
                          bool relayout = true);
