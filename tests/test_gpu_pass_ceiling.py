@@ -45,3 +45,16 @@ def test_empty_pass_rejects_bad_shapes(P):
             P.sv_pass_ceiling(st.h, tb, nph)
         assert P.STATUS[ei.value.status] == "EINVAL"
     st.close()
+
+
+@pytest.mark.parametrize("n16", [1, 2047, 2048, 3 * 2048 + 17, 1 << 20])
+def test_device_copy_exact(P, n16):
+    """The reference copy moves exactly bytes = 16 * n16 (ragged tails too)
+    and leaves the bytes after it alone."""
+    import torch
+    src = torch.randint(0, 1 << 30, (n16 * 4 + 4,), dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    P.sv_device_copy(src.data_ptr(), dst.data_ptr(), 16 * n16, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:n16 * 4], src[:n16 * 4])
+    assert int(dst[n16 * 4:].abs().sum()) == 0
