@@ -168,8 +168,8 @@ svq_status sv_apply_circuit(svq_state st, const svq_gate *gates, int m, const do
  * with dev_buf).  Host-side plans are cached on the handle as usual.  Every
  * call on one GPU shares that GPU's array: calls that overlap on one GPU (two
  * streams or threads) race and must be serialised by the caller.  Errors: as
- * sv_apply_circuit, plus ESHAPE when the tables exceed 4 MiB (about 11,000
- * gates at 352 bytes each; nothing runs then). */
+ * sv_apply_circuit, plus ESHAPE when the tables exceed 4 MiB (about 10,900
+ * gates at 384 bytes each; nothing runs then). */
 svq_status sv_apply_circuit_static(svq_state st, const svq_gate *gates, int m,
                                    const double *theta, int n_theta, svq_sched sched,
                                    int tile_k, svq_stats *stats);

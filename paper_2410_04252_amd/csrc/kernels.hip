@@ -100,9 +100,9 @@ __device__ __forceinline__ void swap_reg(double &a, double &b) {
     put_reg(b, t);
 }
 
-template <int B, typename R, int NR>
-__device__ __forceinline__ void op_diag1(Regs<R, NR> &v, const OpDesc &o) {
-    const R t0 = (R)o.m[16], s0 = (R)o.m[17], t1 = (R)o.m[18], s1 = (R)o.m[19];
+template <int B, typename R, int NR, typename OP>
+__device__ __forceinline__ void op_diag1(Regs<R, NR> &v, const OP &o) {
+    const R t0 = (R)o.sh[0], s0 = (R)o.sh[1], t1 = (R)o.sh[2], s1 = (R)o.sh[3];
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if ((j >> B) & 1) shear_rot(v.re[j], v.im[j], t1, s1);
@@ -120,9 +120,9 @@ __device__ __forceinline__ void op_diag1(Regs<R, NR> &v, const OpDesc &o) {
     }
 }
 
-template <int B0, int B1, typename R, int NR>
-__device__ __forceinline__ void op_cphase(Regs<R, NR> &v, const OpDesc &o) {
-    const R t = (R)o.m[16], sn = (R)o.m[17];
+template <int B0, int B1, typename R, int NR, typename OP>
+__device__ __forceinline__ void op_cphase(Regs<R, NR> &v, const OP &o) {
+    const R t = (R)o.sh[0], sn = (R)o.sh[1];
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (!((j >> B0) & 1) || !((j >> B1) & 1)) continue;
@@ -158,9 +158,9 @@ __device__ __forceinline__ void op_mix1(Regs<R, NR> &v, const OpDesc &o) {
     }
 }
 
-template <int B, typename R, int NR>
-__device__ __forceinline__ void op_roty(Regs<R, NR> &v, const OpDesc &o) {
-    const R t = (R)o.m[16], sn = (R)o.m[17];
+template <int B, typename R, int NR, typename OP>
+__device__ __forceinline__ void op_roty(Regs<R, NR> &v, const OP &o) {
+    const R t = (R)o.sh[0], sn = (R)o.sh[1];
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j & (1 << B)) continue;
@@ -177,8 +177,8 @@ __device__ __forceinline__ void op_roty(Regs<R, NR> &v, const OpDesc &o) {
     }
 }
 
-template <int B, typename R, int NR>
-__device__ __forceinline__ void op_xswap(Regs<R, NR> &v, const OpDesc &) {
+template <int B, typename R, int NR, typename OP>
+__device__ __forceinline__ void op_xswap(Regs<R, NR> &v, const OP &) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j & (1 << B)) continue;
@@ -188,8 +188,8 @@ __device__ __forceinline__ void op_xswap(Regs<R, NR> &v, const OpDesc &) {
     }
 }
 
-template <int B0, int B1, typename R, int NR>
-__device__ __forceinline__ void op_cnot(Regs<R, NR> &v, const OpDesc &) {
+template <int B0, int B1, typename R, int NR, typename OP>
+__device__ __forceinline__ void op_cnot(Regs<R, NR> &v, const OP &) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (!((j >> B0) & 1) || ((j >> B1) & 1)) continue;
@@ -199,9 +199,9 @@ __device__ __forceinline__ void op_cnot(Regs<R, NR> &v, const OpDesc &) {
     }
 }
 
-template <int B0, int B1, typename R, int NR>
-__device__ __forceinline__ void op_givens(Regs<R, NR> &v, const OpDesc &o) {
-    const R t = (R)o.m[16], sn = (R)o.m[17];
+template <int B0, int B1, typename R, int NR, typename OP>
+__device__ __forceinline__ void op_givens(Regs<R, NR> &v, const OP &o) {
+    const R t = (R)o.sh[0], sn = (R)o.sh[1];
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j & ((1 << B0) | (1 << B1))) continue;
@@ -277,18 +277,48 @@ __device__ __forceinline__ void op_mix2(Regs<R, NR> &v, const OpDesc &o) {
 #define SVQ_ROW(FN, I) SVQ_C2(FN, I, 0) SVQ_C2(FN, I, 1) SVQ_C2(FN, I, 2) SVQ_C2(FN, I, 3) SVQ_C2(FN, I, 4)
 #define SVQ_ALL2(FN) SVQ_ROW(FN, 0) SVQ_ROW(FN, 1) SVQ_ROW(FN, 2) SVQ_ROW(FN, 3) SVQ_ROW(FN, 4)
 
+// The code and shear parameters of an op: the first 64 bytes of its
+// descriptor, read with one scalar load before the dispatch (otherwise the
+// parameters are fetched inside the handler, a second load that waits on the
+// first).
+struct OpHead {
+    int32_t type, b0, b1, flip;
+    double sh[4];
+};
+
+#define SVQ_H1(FN, I)                                        \
+    case I:                                                  \
+        if constexpr (I < RB) FN<I, R, NR>(v, h);            \
+        break;
+#define SVQ_H2(FN, I, J)                                                      \
+    case I * 8 + J:                                                           \
+        if constexpr (I < RB && J < RB && I != J) FN<I, J, R, NR>(v, h);      \
+        break;
+#define SVQ_HALL1(FN) SVQ_H1(FN, 0) SVQ_H1(FN, 1) SVQ_H1(FN, 2) SVQ_H1(FN, 3) SVQ_H1(FN, 4)
+#define SVQ_HROW(FN, I) SVQ_H2(FN, I, 0) SVQ_H2(FN, I, 1) SVQ_H2(FN, I, 2) SVQ_H2(FN, I, 3) SVQ_H2(FN, I, 4)
+#define SVQ_HALL2(FN) SVQ_HROW(FN, 0) SVQ_HROW(FN, 1) SVQ_HROW(FN, 2) SVQ_HROW(FN, 3) SVQ_HROW(FN, 4)
+
 template <typename R, int NR, int RB>
 __device__ __forceinline__ void apply_op(Regs<R, NR> &v, const OpDesc &o) {
     static_assert(RB <= 5, "dispatch covers at most 5 register bits");
-    const int b2 = o.b0 * 8 + o.b1;
-    switch (o.type) {
-    case OP_DIAG1: switch (o.b0) { SVQ_ALL1(op_diag1) } break;
-    case OP_MIX1: switch (o.b0) { SVQ_ALL1(op_mix1) } break;
-    case OP_ROTY: switch (o.b0) { SVQ_ALL1(op_roty) } break;
-    case OP_XSWAP: switch (o.b0) { SVQ_ALL1(op_xswap) } break;
-    case OP_CPHASE: switch (b2) { SVQ_ALL2(op_cphase) } break;
-    case OP_CNOT: switch (b2) { SVQ_ALL2(op_cnot) } break;
-    case OP_GIVENS: switch (b2) { SVQ_ALL2(op_givens) } break;
+    OpHead h;
+    h.type = o.type;
+    h.b0 = o.b0;
+    h.b1 = o.b1;
+    h.flip = o.flip;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) h.sh[i] = o.sh[i];
+    asm volatile("" ::"s"(h.type), "s"(h.b0), "s"(h.b1), "s"(h.flip), "s"(h.sh[0]), "s"(h.sh[1]),
+                 "s"(h.sh[2]), "s"(h.sh[3]));
+    const int b2 = h.b0 * 8 + h.b1;
+    switch (h.type) {
+    case OP_DIAG1: switch (h.b0) { SVQ_HALL1(op_diag1) } break;
+    case OP_MIX1: switch (h.b0) { SVQ_ALL1(op_mix1) } break;
+    case OP_ROTY: switch (h.b0) { SVQ_HALL1(op_roty) } break;
+    case OP_XSWAP: switch (h.b0) { SVQ_HALL1(op_xswap) } break;
+    case OP_CPHASE: switch (b2) { SVQ_HALL2(op_cphase) } break;
+    case OP_CNOT: switch (b2) { SVQ_HALL2(op_cnot) } break;
+    case OP_GIVENS: switch (b2) { SVQ_HALL2(op_givens) } break;
     default: switch (b2) { SVQ_ALL2(op_mix2) } break;
     }
 }

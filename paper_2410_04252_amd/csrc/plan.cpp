@@ -1246,8 +1246,8 @@ static void set_shear(OpDesc &o, int i, double c, double s) {
         s = -s;
         o.flip |= 1 << i;
     }
-    o.m[16 + 2 * i] = s / (1.0 + c);
-    o.m[17 + 2 * i] = s;
+    o.sh[2 * i] = s / (1.0 + c);
+    o.sh[2 * i + 1] = s;
 }
 
 static void set_shears(OpDesc &o) {

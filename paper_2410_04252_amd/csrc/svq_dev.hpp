@@ -78,6 +78,9 @@ struct OpDesc {
     int32_t gslot;   // adjoint: slot of this gate in the gradient partials (-1: none)
     int32_t gtype;   // GenType
     int32_t pad;
+    // shear parameters (t, s) of one or two rotations, next to the header so
+    // that one scalar load brings an op's code and its parameters
+    double sh[4];
     double m[32];
     double k[8];
 };

@@ -54,7 +54,7 @@ def test_static_equals_allocating_entry_point_twice(P):
 
 
 def test_static_refuses_tables_beyond_the_scratch(P):
-    """13,000 gates need about 4.6 MB of op descriptors, more than the 4 MiB
+    """13,000 gates need about 5.0 MB of op descriptors, more than the 4 MiB
     scratch: ESHAPE, and the state is left as it was."""
     n, g = 10, 1
     circ = W.random_circuit(n, 13000, 7105)
