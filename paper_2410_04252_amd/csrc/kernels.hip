@@ -291,7 +291,7 @@ struct OpHead {
         if constexpr (I < RB) FN<I, R, NR>(v, h);            \
         break;
 #define SVQ_H2(FN, I, J)                                                      \
-    case I * 8 + J:                                                           \
+    case (I < RB && J < RB) ? I * RB + J : 64 + I * 8 + J:                    \
         if constexpr (I < RB && J < RB && I != J) FN<I, J, R, NR>(v, h);      \
         break;
 #define SVQ_HALL1(FN) SVQ_H1(FN, 0) SVQ_H1(FN, 1) SVQ_H1(FN, 2) SVQ_H1(FN, 3) SVQ_H1(FN, 4)
@@ -310,16 +310,24 @@ __device__ __forceinline__ void apply_op(Regs<R, NR> &v, const OpDesc &o) {
     for (int i = 0; i < 4; ++i) h.sh[i] = o.sh[i];
     asm volatile("" ::"s"(h.type), "s"(h.b0), "s"(h.b1), "s"(h.flip), "s"(h.sh[0]), "s"(h.sh[1]),
                  "s"(h.sh[2]), "s"(h.sh[3]));
-    const int b2 = h.b0 * 8 + h.b1;
+    const int b2 = h.b0 * RB + h.b1;   // the dense key of SVQ_H2
+    const int b2o = h.b0 * 8 + h.b1;   // the key of SVQ_C2 (dense ops)
+    // the two kinds of a fabric circuit first, then the rest
+    if (h.type == OP_GIVENS) {
+        switch (b2) { SVQ_HALL2(op_givens) }
+        return;
+    }
+    if (h.type == OP_CPHASE) {
+        switch (b2) { SVQ_HALL2(op_cphase) }
+        return;
+    }
     switch (h.type) {
     case OP_DIAG1: switch (h.b0) { SVQ_HALL1(op_diag1) } break;
     case OP_MIX1: switch (h.b0) { SVQ_ALL1(op_mix1) } break;
     case OP_ROTY: switch (h.b0) { SVQ_HALL1(op_roty) } break;
     case OP_XSWAP: switch (h.b0) { SVQ_HALL1(op_xswap) } break;
-    case OP_CPHASE: switch (b2) { SVQ_HALL2(op_cphase) } break;
     case OP_CNOT: switch (b2) { SVQ_HALL2(op_cnot) } break;
-    case OP_GIVENS: switch (b2) { SVQ_HALL2(op_givens) } break;
-    default: switch (b2) { SVQ_ALL2(op_mix2) } break;
+    default: switch (b2o) { SVQ_ALL2(op_mix2) } break;
     }
 }
 
