@@ -617,6 +617,9 @@ def measure_batch(P, W, torch, args):
     log(f"[bench] batch {run_ms:.2f} ms ({ninst / run_ms * 1e3:.0f} inst/s, p50 {np.percentile(lat, 50):.2f} "
         f"p99 {np.percentile(lat, 99):.2f} ms); one at a time {loop_ms:.1f} ms")
     gbs = batch_bytes / (run_ms * 1e-3) / 1e9
+    ns = np.array([c.n for c, _ in inst])
+    lat_small = float(np.percentile(lat[ns <= 13], 50)) if np.any(ns <= 13) else None
+    lat_large = float(np.percentile(lat[ns >= 16], 50)) if np.any(ns >= 16) else None
     log(f"[bench] batch algorithmic traffic {batch_bytes / 1e9:.1f} GB per run: {gbs:.0f} GB/s "
         f"({gbs / HBM_PEAK_GBS * 100:.1f}% of HBM peak), {n_stages} stages, {n_items} items")
     return dict(workload="batch256", instances=ninst, create_ms=create_ms, tuned=tuned,
@@ -624,6 +627,7 @@ def measure_batch(P, W, torch, args):
                 algorithmic_bytes=batch_bytes, algorithmic_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
                 stages=n_stages, items=n_items, instances_per_s=ninst / run_ms * 1e3,
                 latency_p50_ms=float(np.percentile(lat, 50)),
+                latency_p50_ms_lds_instances=lat_small, latency_p50_ms_wide_instances=lat_large,
                 latency_p99_ms=float(np.percentile(lat, 99)),
                 loop_ms=loop_ms, loop_instances_per_s=ninst / loop_ms * 1e3,
                 loop_latency_p50_ms=float(np.percentile(done, 50)),

@@ -279,7 +279,10 @@ svq_status sv_plan_paulis(int n, int g, const svq_pauli *terms, int n_terms, svq
  * into 2^10-amplitude tiles, grouped into items (a range of tiles each).  The
  * graph holds one launch per (stage level, item type): the k-th stages of all
  * instances that are gate passes run in one launch, and so on; stream order
- * carries the dependencies.  With SVQ_BATCH_PERSISTENT=1 in the environment
+ * carries the dependencies.  Instances of at most 13 qubits instead run
+ * whole in one workgroup each, psi and lambda held in LDS (2 x 2^n complex64;
+ * any Pauli string, no tiling), in one launch beside the others.  With
+ * SVQ_BATCH_PERSISTENT=1 in the environment
  * at creation the graph instead holds one persistent launch whose single-wave
  * blocks pull items from a device queue and wait, with a bounded spin, for
  * the instance's previous stage.
@@ -290,7 +293,9 @@ typedef struct svq_batch_s *svq_batch;
 /* gates[i][0..m[i]), theta of instance i has n_theta[i] entries, terms[i]
  * [0..n_terms[i]), psi0[i] the initial basis state.  low_bits = 0 picks the
  * tuned value.  The library allocates the state arena (two states per
- * instance) and tables.  Errors: EINVAL (shapes, gates, masks), ENOMEM, EHIP. */
+ * instance) and tables.  Errors: EINVAL (shapes, gates, masks), EUNSUP (an
+ * instance above 13 qubits with a Pauli string whose X/Y sites fit no
+ * 2^10-amplitude tile), ENOMEM, EHIP. */
 svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *const *gates,
                            const int32_t *m, const int32_t *n_theta,
                            const svq_pauli *const *terms, const int32_t *n_terms,

@@ -1610,6 +1610,11 @@ struct svq_batch_s {
     std::vector<int> ntheta;
     std::vector<int> theta_off;            // offset of each instance in the grads output
     std::vector<OpDesc> ops_fwd, ops_inv;  // filled per run
+    // instances held in LDS: ops in gate order (template), their instance
+    std::vector<OpDesc> lops;
+    std::vector<int> lop_inst;
+    std::vector<BatchLdsInst> linsts;
+    int lds_max_n = 0;
     std::vector<int> op_gate, op_inst;     // gate index / instance of every op
     std::vector<BatchInst> insts;
     int nitems = 0, nstages = 0, total_theta = 0;
@@ -1621,6 +1626,8 @@ struct svq_batch_s {
     DevBuf arena, items, stages, dinsts, passes, hpasses, phases, d_ops_fwd, d_ops_inv, hgroups,
         hterms, pptr, pgate, epart, gpart, energies, grads, counters, t_done, t_start;
     OpDesc *h_ops_fwd = nullptr, *h_ops_inv = nullptr;   // pinned staging
+    OpDesc *h_lops_fwd = nullptr, *h_lops_inv = nullptr;
+    DevBuf d_linst, d_lterms, d_gvals, d_lops_fwd, d_lops_inv;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     BatchArgs args;
@@ -1629,6 +1636,8 @@ struct svq_batch_s {
         if (graph) (void)hipGraphDestroy(graph);
         if (h_ops_fwd) (void)hipHostFree(h_ops_fwd);
         if (h_ops_inv) (void)hipHostFree(h_ops_inv);
+        if (h_lops_fwd) (void)hipHostFree(h_lops_fwd);
+        if (h_lops_inv) (void)hipHostFree(h_lops_inv);
     }
 };
 
@@ -1695,6 +1704,26 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
     TuneVal tw{kBatchWideN, 0, 0.0};
     (void)tuned(3, 0, 0, 0, tw);
     const int wide_n = env_int("SVQ_BATCH_WIDE_N", tw.k);
+    // Small instances keep psi and lambda in one workgroup's LDS for the whole
+    // evaluation (level-synchronous form only).
+    const int lds_n = b->persistent ? 0 : std::min(kBatchLdsN, env_int("SVQ_BATCH_LDS_N", kBatchLdsN));
+    std::vector<WideTerm> lterms;
+    int gv_total = 0;
+    // CSR parameter -> gates (gate indices local to the instance)
+    auto add_csr = [&](int i, const std::vector<GateN> &gn) {
+        const int off = (int)pptr.size();
+        std::vector<std::vector<int>> byp(n_theta[i]);
+        for (int gi = 0; gi < m[i]; ++gi)
+            if (gn[gi].param >= 0 && (gn[gi].kind == SVQ_RX || gn[gi].kind == SVQ_RY || gn[gi].kind == SVQ_RZ ||
+                                      gn[gi].kind == SVQ_CPHASE || gn[gi].kind == SVQ_GIVENS))
+                byp[gn[gi].param].push_back(gi);
+        pptr.push_back((int)pgate.size());
+        for (int p = 0; p < n_theta[i]; ++p) {
+            for (int gi : byp[p]) pgate.push_back(gi);
+            pptr.push_back((int)pgate.size());
+        }
+        return off;
+    };
     for (int i = 0; i < n_inst; ++i) {
         const int n = n_qubits[i];
         const bool wide = !b->persistent && n >= wide_n && n >= kBatchKWide;
@@ -1706,6 +1735,66 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
         std::vector<GateN> gn;
         std::string err = normalize_gates(n, gates[i], m[i], n_theta[i], gn);
         if (!err.empty()) return fail(SVQ_EINVAL, "instance " + std::to_string(i) + ": " + err);
+        if (n <= lds_n) {
+            for (int t = 0; t < n_terms[i]; ++t) {
+                const svq_pauli &tp = terms[i][t];
+                if (((tp.x | tp.z) >> n) || !std::isfinite(tp.coef))
+                    return fail(SVQ_EINVAL, "instance " + std::to_string(i) + ": bad Pauli term");
+            }
+            BatchLdsInst L;
+            std::memset(&L, 0, sizeof(L));
+            L.n = n;
+            L.m = m[i];
+            L.op0 = (int)b->lops.size();
+            L.t0 = (int)lterms.size();
+            L.nt = n_terms[i];
+            L.ntheta = n_theta[i];
+            L.grad_off = b->total_theta;
+            L.gv_off = gv_total;
+            L.inst = i;
+            L.psi0_lo = (uint32_t)psi0[i];
+            L.psi0_hi = (uint32_t)(psi0[i] >> 32);
+            gv_total += std::max(1, m[i]);
+            for (int gi = 0; gi < m[i]; ++gi) {
+                OpDesc o;
+                std::memset(&o, 0, sizeof(o));
+                o.type = op_type_for_kind(gn[gi].kind);
+                o.b0 = 0;
+                o.b1 = gn[gi].nq > 1 ? 1 : 0;
+                o.spare = gn[gi].q[0];
+                o.pad = gn[gi].nq > 1 ? gn[gi].q[1] : -1;
+                o.gslot = -1;
+                b->lops.push_back(o);
+                b->lop_inst.push_back(i);
+            }
+            for (int t = 0; t < n_terms[i]; ++t) {
+                WideTerm w;
+                std::memset(&w, 0, sizeof(w));
+                w.x = terms[i][t].x;
+                w.z = terms[i][t].z;
+                w.coef = terms[i][t].coef;
+                w.ny = __builtin_popcountll(terms[i][t].x & terms[i][t].z);
+                lterms.push_back(w);
+            }
+            L.pptr_off = add_csr(i, gn);
+            BatchInst I;
+            std::memset(&I, 0, sizeof(I));
+            I.n = n;
+            I.stage0 = (int)stages.size();
+            I.nstages = 0;
+            I.m = m[i];
+            I.ntheta = n_theta[i];
+            I.grad_off = b->total_theta;
+            inst_stage_count[i] = 0;
+            b->theta_off.push_back(b->total_theta);
+            b->total_theta += n_theta[i];
+            b->linsts.push_back(L);
+            b->lds_max_n = std::max(b->lds_max_n, n);
+            b->gates.push_back(std::move(gn));
+            b->ntheta.push_back(n_theta[i]);
+            b->insts.push_back(I);
+            continue;
+        }
         std::vector<int> pos(n);
         for (int q = 0; q < n; ++q) pos[q] = q;
         CircuitPlan cp;
@@ -1805,18 +1894,7 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
                                      4.0 * cp.passes.size());
         }
         inst_stage_count[i] = I.nstages;
-        // CSR parameter -> gates (gate indices local to the instance)
-        I.pptr_off = (int)pptr.size();
-        std::vector<std::vector<int>> byp(n_theta[i]);
-        for (int gi = 0; gi < m[i]; ++gi)
-            if (gn[gi].param >= 0 && (gn[gi].kind == SVQ_RX || gn[gi].kind == SVQ_RY || gn[gi].kind == SVQ_RZ ||
-                                      gn[gi].kind == SVQ_CPHASE || gn[gi].kind == SVQ_GIVENS))
-                byp[gn[gi].param].push_back(gi);
-        pptr.push_back((int)pgate.size());
-        for (int p = 0; p < n_theta[i]; ++p) {
-            for (int gi : byp[p]) pgate.push_back(gi);
-            pptr.push_back((int)pgate.size());
-        }
+        I.pptr_off = add_csr(i, gn);
         b->gates.push_back(std::move(gn));
         b->ntheta.push_back(n_theta[i]);
         b->insts.push_back(I);
@@ -1880,6 +1958,17 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
     BHIPCHK(bp, b->t_start.ensure(sizeof(uint64_t)), "alloc time");
     BHIPCHK(bp, hipHostMalloc((void **)&b->h_ops_fwd, sizeof(OpDesc) * std::max<size_t>(1, b->ops_fwd.size())), "pinned ops");
     BHIPCHK(bp, hipHostMalloc((void **)&b->h_ops_inv, sizeof(OpDesc) * std::max<size_t>(1, b->ops_fwd.size())), "pinned ops");
+    if (!b->linsts.empty()) {
+        const size_t nl = std::max<size_t>(1, b->lops.size());
+        BHIPCHK(bp, upload(b->d_linst, b->linsts, s), "upload LDS instances");
+        BHIPCHK(bp, upload(b->d_lterms, lterms, s), "upload LDS terms");
+        BHIPCHK(bp, b->d_gvals.ensure(sizeof(double) * std::max(1, gv_total)), "alloc gradient slots");
+        BHIPCHK(bp, b->d_lops_fwd.ensure(sizeof(OpDesc) * nl), "alloc ops");
+        BHIPCHK(bp, b->d_lops_inv.ensure(sizeof(OpDesc) * nl), "alloc ops");
+        BHIPCHK(bp, hipHostMalloc((void **)&b->h_lops_fwd, sizeof(OpDesc) * nl), "pinned ops");
+        BHIPCHK(bp, hipHostMalloc((void **)&b->h_lops_inv, sizeof(OpDesc) * nl), "pinned ops");
+        BHIPCHK(bp, prepare_batch_lds(b->lds_max_n), "LDS limit");
+    }
     BHIPCHK(bp, hipStreamSynchronize(s), "sync");
     BatchArgs &A = b->args;
     std::memset(&A, 0, sizeof(A));
@@ -1907,6 +1996,11 @@ svq_status sv_batch_create(int n_inst, const int32_t *n_qubits, const svq_gate *
     A.t_start = (uint64_t *)b->t_start.p;
     A.nitems = b->nitems;
     A.spin_limit = env_int("SVQ_BATCH_SPIN_LIMIT", kBatchSpinLimit);
+    A.linst = (const BatchLdsInst *)b->d_linst.p;
+    A.lops_fwd = (const OpDesc *)b->d_lops_fwd.p;
+    A.lops_inv = (const OpDesc *)b->d_lops_inv.p;
+    A.lterms = b->d_lterms.p;
+    A.gvals = (double *)b->d_gvals.p;
     *out = b.release();
     return SVQ_OK;
 }
@@ -1941,6 +2035,29 @@ svq_status sv_batch_run(svq_batch b, const double *const *theta, double *energie
         std::memcpy(b->h_ops_inv + o, inv.data(), sizeof(OpDesc) * inv.size());
         o = o1;
     }
+    // LDS instances: ops in gate order
+    for (size_t o = 0; o < b->lops.size();) {
+        const int i = b->lop_inst[o];
+        size_t o1 = o;
+        while (o1 < b->lops.size() && b->lop_inst[o1] == i) ++o1;
+        std::vector<OpDesc> f(b->lops.begin() + o, b->lops.begin() + o1);
+        std::vector<int> og(f.size());
+        for (size_t j = 0; j < og.size(); ++j) og[j] = (int)j;
+        std::vector<OpDesc> inv = f;
+        fill_ops(b->gates[i], theta[i], og, f, false);
+        fill_ops(b->gates[i], theta[i], og, inv, true);
+        for (size_t j = 0; j < inv.size(); ++j) {
+            const GateN &g = b->gates[i][j];
+            if (!(g.param >= 0 && inv[j].gtype != GEN_NONE)) inv[j].gtype = GEN_NONE;
+        }
+        std::memcpy(b->h_lops_fwd + o, f.data(), sizeof(OpDesc) * f.size());
+        std::memcpy(b->h_lops_inv + o, inv.data(), sizeof(OpDesc) * inv.size());
+        o = o1;
+    }
+    if (!b->lops.empty()) {
+        BHIPCHK(b, hipMemcpyAsync(b->d_lops_fwd.p, b->h_lops_fwd, sizeof(OpDesc) * b->lops.size(), hipMemcpyHostToDevice, b->stream), "upload ops");
+        BHIPCHK(b, hipMemcpyAsync(b->d_lops_inv.p, b->h_lops_inv, sizeof(OpDesc) * b->lops.size(), hipMemcpyHostToDevice, b->stream), "upload ops");
+    }
     const size_t nops = b->ops_fwd.size();
     if (nops) {
         BHIPCHK(b, hipMemcpyAsync(b->d_ops_fwd.p, b->h_ops_fwd, sizeof(OpDesc) * nops, hipMemcpyHostToDevice, b->stream), "upload ops");
@@ -1966,7 +2083,7 @@ svq_status sv_batch_run(svq_batch b, const double *const *theta, double *energie
         if (le == hipSuccess && !b->persistent) {
             // the error flag stays zero: these launches never wait
             le = launch_fill_i32((int32_t *)b->counters.p, b->nstages + 2, 0, cap);
-            bool cls_used[2] = {false, false};
+            bool cls_used[2] = {!b->linsts.empty(), false};
             for (const auto &gr : b->groups) cls_used[gr[3]] = true;
             const bool branch = cls_used[0] && cls_used[1];
             if (branch && le == hipSuccess) le = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
@@ -1974,6 +2091,8 @@ svq_status sv_batch_run(svq_batch b, const double *const *theta, double *energie
             if (branch && le == hipSuccess) le = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
             if (branch && le == hipSuccess) le = hipEventRecord(fork, cap);
             if (branch && le == hipSuccess) le = hipStreamWaitEvent(side, fork, 0);
+            if (le == hipSuccess)
+                le = launch_batch_lds(b->args, (int)b->linsts.size(), b->lds_max_n, branch ? side : cap);
             for (size_t gi = 0; gi < b->groups.size() && le == hipSuccess; ++gi) {
                 const auto &gr = b->groups[gi];
                 le = launch_batch_stage(b->args, gr[0], gr[1], gr[2], (branch && gr[3] == 0) ? side : cap);

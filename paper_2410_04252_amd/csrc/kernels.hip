@@ -1879,6 +1879,155 @@ k_batch_stage(const BatchArgs a, int item0) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// batched instances held in one workgroup's LDS
+// ---------------------------------------------------------------------------
+
+namespace lds_batch {
+
+// Index of pair/quad p with zeros inserted at the gate's qubits.
+__device__ __forceinline__ uint32_t insert0(uint32_t p, int q) {
+    const uint32_t lo = p & ((1u << q) - 1u);
+    return ((p >> q) << (q + 1)) | lo;
+}
+
+__device__ __forceinline__ double block_sum_all(double v, double *red) {
+    v = wave_sum(v);
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBatchLdsThreads / 64; ++w) s += red[w];
+    return s;
+}
+
+// One op over the LDS state(s): 1-qubit ops on pairs (register bit 0 on the
+// qubit), 2-qubit ops on quads (register bits 0/1 on the first/second
+// qubit).  With ADJ the op's gradient term 2 Im <lambda|K|psi> is returned
+// (this thread's part) before U^dagger is applied to both.
+template <bool ADJ, int NRT, int RBT>
+__device__ __forceinline__ double op_on_lds(float2 *psi, float2 *lam, const OpDesc &o, uint32_t S) {
+    const int q0 = o.spare, q1 = o.pad;
+    double g = 0.0;
+    const uint32_t nitems = S >> RBT;
+    for (uint32_t p = threadIdx.x; p < nitems; p += kBatchLdsThreads) {
+        uint32_t base;
+        if constexpr (RBT == 1) {
+            base = insert0(p, q0);
+        } else {
+            const int lo = q0 < q1 ? q0 : q1, hi = q0 < q1 ? q1 : q0;
+            base = insert0(insert0(p, lo), hi);
+        }
+        uint32_t idx[NRT];
+#pragma unroll
+        for (int j = 0; j < NRT; ++j) {
+            idx[j] = base;
+            if (j & 1) idx[j] |= 1u << q0;
+            if constexpr (RBT == 2) {
+                if (j & 2) idx[j] |= 1u << q1;
+            }
+        }
+        Regs<float, NRT> v, w;
+#pragma unroll
+        for (int j = 0; j < NRT; ++j) {
+            const float2 e = psi[idx[j]];
+            v.re[j] = e.x;
+            v.im[j] = e.y;
+            if constexpr (ADJ) {
+                const float2 f = lam[idx[j]];
+                w.re[j] = f.x;
+                w.im[j] = f.y;
+            }
+        }
+        if constexpr (ADJ) {
+            if (o.gtype != GEN_NONE) g += op_gradient<float, NRT, RBT>(v, w, o);
+            apply_op<float, NRT, RBT>(w, o);
+        }
+        apply_op<float, NRT, RBT>(v, o);
+#pragma unroll
+        for (int j = 0; j < NRT; ++j) {
+            psi[idx[j]] = make_float2(v.re[j], v.im[j]);
+            if constexpr (ADJ) lam[idx[j]] = make_float2(w.re[j], w.im[j]);
+        }
+    }
+    return g;
+}
+
+}  // namespace lds_batch
+
+// One block per instance: psi0, the gates in order, lambda = H psi (FP64 per
+// element), E, then the reverse sweep with each parametric gate's gradient
+// term summed over the block in a fixed order, and the per-parameter sums.
+// psi and lambda stay in LDS throughout.
+__global__ __launch_bounds__(kBatchLdsThreads) void k_batch_lds(const BatchArgs a) {
+    extern __shared__ float2 smem[];
+    __shared__ double red[kBatchLdsThreads / 64];
+    const BatchLdsInst L = a.linst[blockIdx.x];
+    const uint32_t S = 1u << L.n;
+    float2 *psi = smem, *lam = smem + S;
+    const WideTerm *terms = (const WideTerm *)a.lterms;
+    const uint64_t idx0 = ((uint64_t)L.psi0_hi << 32) | L.psi0_lo;
+    for (uint32_t e = threadIdx.x; e < S; e += kBatchLdsThreads)
+        psi[e] = make_float2(e == idx0 ? 1.f : 0.f, 0.f);
+    __syncthreads();
+    for (int gi = 0; gi < L.m; ++gi) {
+        const OpDesc &o = a.lops_fwd[L.op0 + gi];
+        if (o.pad < 0) (void)lds_batch::op_on_lds<false, 2, 1>(psi, nullptr, o, S);
+        else (void)lds_batch::op_on_lds<false, 4, 2>(psi, nullptr, o, S);
+        __syncthreads();
+    }
+    // lambda = H psi and E = Re <psi|lambda>
+    double eacc = 0.0;
+    for (uint32_t e = threadIdx.x; e < S; e += kBatchLdsThreads) {
+        double ar = 0.0, ai = 0.0;
+        for (int t = L.t0; t < L.t0 + L.nt; ++t) {
+            const WideTerm &T = terms[t];
+            const uint32_t src = e ^ (uint32_t)T.x;
+            const float2 p = psi[src];
+            const double sg = (__builtin_popcount(src & (uint32_t)T.z) & 1) ? -T.coef : T.coef;
+            double qr, qi;
+            switch (T.ny & 3) {
+            case 0: qr = p.x; qi = p.y; break;
+            case 1: qr = -p.y; qi = p.x; break;
+            case 2: qr = -p.x; qi = -p.y; break;
+            default: qr = p.y; qi = -p.x; break;
+            }
+            ar += sg * qr;
+            ai += sg * qi;
+        }
+        const float2 me = psi[e];
+        eacc += (double)me.x * ar + (double)me.y * ai;
+        lam[e] = make_float2((float)ar, (float)ai);
+    }
+    const double E = lds_batch::block_sum_all(eacc, red);
+    if (threadIdx.x == 0) a.energies[L.inst] = E;
+    __syncthreads();
+    for (int gi = L.m - 1; gi >= 0; --gi) {
+        const OpDesc &o = a.lops_inv[L.op0 + gi];
+        double gp;
+        if (o.pad < 0) gp = lds_batch::op_on_lds<true, 2, 1>(psi, lam, o, S);
+        else gp = lds_batch::op_on_lds<true, 4, 2>(psi, lam, o, S);
+        if (o.gtype != GEN_NONE) {
+            const double gsum = lds_batch::block_sum_all(gp, red);
+            if (threadIdx.x == 0) a.gvals[L.gv_off + gi] = gsum;
+        }
+        __syncthreads();
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int p = threadIdx.x; p < L.ntheta; p += kBatchLdsThreads) {
+        double g = 0.0;
+        for (int q = a.pptr[L.pptr_off + p]; q < a.pptr[L.pptr_off + p + 1]; ++q)
+            g += a.gvals[L.gv_off + a.pgate[q]];
+        a.grads[L.grad_off + p] = g;
+    }
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_max(a.t_done + L.inst, (uint64_t)__builtin_amdgcn_s_memrealtime(), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
@@ -1894,6 +2043,18 @@ hipError_t launch_batch(const BatchArgs &a, int32_t *counters, int ncounters, hi
     const int grid = per_cu * num_cu();
     if (grid_out) *grid_out = grid;
     hipLaunchKernelGGL(k_batch, dim3(grid), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t prepare_batch_lds(int max_n) {
+    const size_t bytes = sizeof(float2) * ((size_t)2 << max_n);
+    return hipFuncSetAttribute((const void *)k_batch_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_batch_lds(const BatchArgs &a, int ninst, int max_n, hipStream_t s) {
+    if (ninst <= 0) return hipSuccess;
+    const size_t bytes = sizeof(float2) * ((size_t)2 << max_n);
+    hipLaunchKernelGGL(k_batch_lds, dim3(ninst), dim3(kBatchLdsThreads), bytes, s, a);
     return hipGetLastError();
 }
 

@@ -71,6 +71,11 @@ hipError_t launch_fill_basis(bool dbl, void *psi, uint64_t N, uint64_t idx, hipS
 // Reset counters (fill kernel) and launch the persistent batch kernel.
 hipError_t launch_batch(const BatchArgs &a, int32_t *counters, int ncounters, hipStream_t s,
                         int *grid_out);
+// One block per LDS-resident instance (a.linst[0, ninst)), 2 x 2^max_n
+// complex64 of dynamic LDS; prepare_batch_lds(max_n) first (outside any
+// stream capture) raises the kernel's dynamic LDS limit.
+hipError_t prepare_batch_lds(int max_n);
+hipError_t launch_batch_lds(const BatchArgs &a, int ninst, int max_n, hipStream_t s);
 // p[0, n) = v with a fill kernel (no memset node in a captured graph).
 hipError_t launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s);
 // One level-synchronous launch: items [item0, item0 + nitem), all of one type.

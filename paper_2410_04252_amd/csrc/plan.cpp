@@ -679,6 +679,8 @@ static int op_type_of(int kind) {
     }
 }
 
+int op_type_for_kind(int kind) { return op_type_of(kind); }
+
 // Lanes of a load or store phase: the required tile bits (those on the
 // lowest physical positions, in position order, so that consecutive lanes
 // address consecutive amplitudes), then free bits preferring residue i mod 6

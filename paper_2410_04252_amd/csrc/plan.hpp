@@ -112,6 +112,9 @@ std::string plan_circuit(int n, int g, const std::vector<GateN> &gates, svq_sche
                          int rb, int c, const std::vector<int> &pos0, CircuitPlan &out,
                          bool relayout = true);
 
+// The op type that applies gates of this kind (OpType).
+int op_type_for_kind(int kind);
+
 // Fill op coefficients for the given angles (forward).  For the adjoint sweep
 // `inverse` fills U^dagger and the generator data.
 void fill_ops(const std::vector<GateN> &gates, const double *theta, const std::vector<int> &op_gate,

@@ -187,6 +187,8 @@ namespace svq {
 constexpr int kBatchK = 10;          // tile bits of the batched stages
 constexpr int kBatchKWide = 12;      // tile bits of the gate passes of large instances
 constexpr int kBatchWideN = 16;      // instances of at least this many qubits use them
+constexpr int kBatchLdsN = 13;       // instances of at most this many qubits run in LDS
+constexpr int kBatchLdsThreads = 512;
 constexpr int kBatchSpinLimit = 1 << 24;
 
 enum ItemType : int32_t {
@@ -240,6 +242,16 @@ struct BatchInst {
     int32_t grad_off, pad;
 };
 
+// An instance evaluated entirely in one workgroup's LDS (psi and lambda,
+// 2 x 2^n complex64).  Its ops are in gate order with the gate's qubits on
+// register bits 0/1 (OpDesc::spare = first qubit, OpDesc::pad = second or -1).
+struct BatchLdsInst {
+    int32_t n, m, op0, t0;        // qubits, gates, first op, first term
+    int32_t nt, ntheta, grad_off, pptr_off;
+    int32_t gv_off, inst;         // per-gate gradient slots; index in the batch
+    uint32_t psi0_lo, psi0_hi;
+};
+
 struct BatchArgs {
     float2 *arena;
     const BatchItem *items;
@@ -265,6 +277,12 @@ struct BatchArgs {
     uint64_t *t_start;        // realtime clock when the first block started
     int32_t nitems;
     int32_t spin_limit;
+    // instances held in LDS (k_batch_lds)
+    const BatchLdsInst *linst;
+    const OpDesc *lops_fwd;
+    const OpDesc *lops_inv;
+    const void *lterms;       // WideTerm[] in logical (= physical) order
+    double *gvals;            // per gate of an LDS instance: 2 Im <lambda|K|psi>
 };
 
 }  // namespace svq

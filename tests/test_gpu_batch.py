@@ -72,6 +72,41 @@ def test_batch_equals_one_at_a_time(P):
     b.close()
 
 
+def test_lds_instances_with_wide_strings_match_oracle(P):
+    """Instances of at most 13 qubits run in one workgroup's LDS and take any
+    Pauli string, including one with X/Y on every qubit (which fits no tile
+    of the tiled path), dense gates and scaled shared parameters.  200
+    Jordan-Wigner-like strings per instance, the regime the complex64
+    tolerance floor is set for."""
+    inst = []
+    for i, n in enumerate((10, 11, 12, 13)):
+        base = W.fabric(n, 4, 6100 + i)
+        gates = []
+        for j, (kind, qs, p) in enumerate(base.gates):
+            gates.append((kind, qs, p, 0.1 * (j % 3), (0.5, 1.0, -2.0)[j % 3]) if p >= 0 else (kind, qs, p))
+        rng = np.random.default_rng(6200 + i)
+        u = np.linalg.qr(rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2)))[0]
+        gates.append(("U1", (n - 1,), -1, u))
+        circ = W.Circuit(n, gates, base.theta, base.psi0_index)
+        h = W.jw_terms(n, 200, 6300 + i)
+        full = (1 << n) - 1
+        ham = W.Hamiltonian(n, np.concatenate([h.x, np.array([full, full ^ 5], dtype=np.uint64)]),
+                            np.concatenate([h.z, np.array([0b1010, full], dtype=np.uint64)]),
+                            np.concatenate([h.coef, np.array([0.3, -0.2])]))
+        inst.append((circ, ham))
+    print("LDS instances with wide strings", flush=True)
+    b = P.Batch(inst)
+    e, grads, lat = b.run()
+    b.close()
+    for i, (c, h) in enumerate(inst):
+        e_ref, g_ref = oracle.adjoint_grad(c, h)
+        ok, rel = energy_ok(e[i], e_ref, None, h, "c64")
+        assert ok, (i, rel)
+        ok, grel = grad_ok(grads[i], g_ref, h, "c64")
+        assert ok, (i, grel)
+    assert np.all(lat > 0)
+
+
 def test_persistent_batch_matches_level_synchronous(P, monkeypatch):
     """The persistent form (one launch, a device queue, bounded waits) gives
     the level-synchronous form's energies and gradients."""

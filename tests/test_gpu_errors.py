@@ -79,10 +79,11 @@ def test_eshape(P):
 
 
 def test_eunsup_batch_instance_needing_a_wide_term(P):
-    """A batch instance keeps all qubits local (no reorder): a 12-qubit
-    string with X on every qubit fits no 2^10 tile."""
-    circ = W.fabric(12, 2, 905)
-    ham = W.Hamiltonian(12, np.array([(1 << 12) - 1], dtype=np.uint64),
+    """A batch instance keeps all qubits local (no reorder): a 14-qubit
+    string with X on every qubit fits no 2^10 tile (instances of at most 13
+    qubits are held in LDS and take any string)."""
+    circ = W.fabric(14, 2, 905)
+    ham = W.Hamiltonian(14, np.array([(1 << 14) - 1], dtype=np.uint64),
                         np.array([0], dtype=np.uint64), np.array([0.5]))
     with pytest.raises(P.SvqError) as ei:
         P.Batch([(circ, ham)])
