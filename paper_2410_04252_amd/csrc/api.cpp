@@ -2083,6 +2083,7 @@ svq_status sv_batch_run(svq_batch b, const double *const *theta, double *energie
         if (le == hipSuccess && !b->persistent) {
             // the error flag stays zero: these launches never wait
             le = launch_fill_i32((int32_t *)b->counters.p, b->nstages + 2, 0, cap);
+            if (le == hipSuccess) le = launch_stamp((uint64_t *)b->t_start.p, cap);   // before the fork
             bool cls_used[2] = {!b->linsts.empty(), false};
             for (const auto &gr : b->groups) cls_used[gr[3]] = true;
             const bool branch = cls_used[0] && cls_used[1];

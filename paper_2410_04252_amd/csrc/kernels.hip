@@ -1854,9 +1854,6 @@ k_batch_stage(const BatchArgs a, int item0) {
     const BatchItem I = a.items[item0 + (int)blockIdx.x];
     const BatchInst &N = a.insts[I.inst];
     const BatchStage S = a.stages[N.stage0 + I.stage];
-    if constexpr (TYPE == IT_INIT) {
-        if (item0 == 0 && blockIdx.x == 0 && lane == 0) *a.t_start = __builtin_amdgcn_s_memrealtime();
-    }
     double dacc = 0.0;
     for (int k = 0; k < I.ntile; ++k) {
         const uint32_t tile = (uint32_t)(I.tile0 + k);
@@ -2055,6 +2052,13 @@ hipError_t launch_batch_lds(const BatchArgs &a, int ninst, int max_n, hipStream_
     if (ninst <= 0) return hipSuccess;
     const size_t bytes = sizeof(float2) * ((size_t)2 << max_n);
     hipLaunchKernelGGL(k_batch_lds, dim3(ninst), dim3(kBatchLdsThreads), bytes, s, a);
+    return hipGetLastError();
+}
+
+__global__ void k_stamp(uint64_t *t) { *t = __builtin_amdgcn_s_memrealtime(); }
+
+hipError_t launch_stamp(uint64_t *t, hipStream_t s) {
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(1), 0, s, t);
     return hipGetLastError();
 }
 

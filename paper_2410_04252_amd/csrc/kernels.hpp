@@ -76,6 +76,8 @@ hipError_t launch_batch(const BatchArgs &a, int32_t *counters, int ncounters, hi
 // stream capture) raises the kernel's dynamic LDS limit.
 hipError_t prepare_batch_lds(int max_n);
 hipError_t launch_batch_lds(const BatchArgs &a, int ninst, int max_n, hipStream_t s);
+// *t = the realtime clock (one thread; the batch graph's start time).
+hipError_t launch_stamp(uint64_t *t, hipStream_t s);
 // p[0, n) = v with a fill kernel (no memset node in a captured graph).
 hipError_t launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s);
 // One level-synchronous launch: items [item0, item0 + nitem), all of one type.

@@ -238,3 +238,19 @@ def test_comm_cost_gatefabric_sweep(P, n):
     assert P.sv_qr_cost(n, nL, n_intra, ops, P.PLAN_HIERARCHICAL)[:2] == hi
     assert hi[1] < fl[1]
     assert S.comm_cost(*hi, 1.0, 30.0) < S.comm_cost(*fl, 1.0, 30.0)
+
+
+def test_qr_cost_rejects_bad_arguments(P):
+    ops = [(0, 1), (2, 3)]
+    for args in ((6, 4, 3, ops, P.PLAN_FLAT),      # n_local + n_intra > n
+                 (6, 4, -1, ops, P.PLAN_FLAT),     # negative n_intra
+                 (6, 4, 1, ops, 7)):               # no such method
+        with pytest.raises(P.SvqError) as ei:
+            P.sv_qr_cost(*args)
+        assert P.STATUS[ei.value.status] == "EINVAL"
+    for w in ((float("nan"), 1.0), (1.0, float("inf")), (-1.0, 10.0)):
+        with pytest.raises(P.SvqError) as ei:
+            P.sv_qr_cost(6, 4, 1, ops, P.PLAN_FLAT, *w)
+        assert P.STATUS[ei.value.status] == "EINVAL"
+    # no reorder at all: zero cost whatever the weights
+    assert P.sv_qr_cost(6, 4, 1, ops, P.PLAN_FLAT, 1.0, 30.0) == (0, 0, 0.0)
