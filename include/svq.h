@@ -336,7 +336,12 @@ svq_status sv_batch_tune(int n_inst, const int32_t *n_qubits, const svq_gate *co
                          const int32_t *m, const int32_t *n_theta, const svq_pauli *const *terms,
                          const int32_t *n_terms, const uint64_t *psi0, const double *const *theta,
                          void *stream, int *chunks_out, int *low_bits_out, double *ms_out);
-/* Persist / restore the tuned table (text: kind n g dtype k c ms per line). */
+/* Persist / restore the tuned table (text: kind n g dtype k c ms per line).
+ * Kinds: 0 gate pass and 1 Pauli pass (k = tile bits, c = low coalescing
+ * bits, per qubit count n, global bits g and dtype 0 = complex64 /
+ * 1 = complex128); 2 batch (k = items per stage, c = low bits); 3 batch size
+ * classes (k = smallest qubit count run on 2^12-amplitude tiles, c = 0).
+ * sv_tune_load skips lines of other kinds or out-of-range values. */
 svq_status sv_tune_save(const char *path);
 svq_status sv_tune_load(const char *path);
 

@@ -270,7 +270,8 @@ svq_status hip_fail(svq_state st, hipError_t e, const char *what) {
     } while (0)
 
 // ---- tuned table: (kind, n, g, dtype) -> (k, c); kind 0 gate pass, 1 Pauli
-// pass, 2 batch (k = items per stage, c = low bits; n = g = 0) ----------------
+// pass, 2 batch (k = items per stage, c = low bits; n = g = 0), 3 batch size
+// classes (k = smallest instance on 2^12 tiles, c = 0; n = g = 0) -------------
 struct TuneKey {
     int kind, n, g, dt;
     bool operator<(const TuneKey &o) const {
@@ -2410,7 +2411,8 @@ svq_status sv_tune_load(const char *path) {
     double ms;
     int cnt = 0;
     while (std::fscanf(f, "%d %d %d %d %d %d %lf", &kind, &n, &g, &dt, &k, &c, &ms) == 7) {
-        if (kind < 0 || kind > 2 || k < 1 || c < 1) continue;
+        // kind 3 (the batch's wide-tile size class) stores no low-bit count
+        if (kind < 0 || kind > 3 || k < 1 || c < (kind == 3 ? 0 : 1)) continue;
         set_tuned(kind, n, g, dt, {k, c, ms});
         ++cnt;
     }

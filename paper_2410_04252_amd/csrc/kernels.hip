@@ -865,24 +865,38 @@ __global__ __launch_bounds__(1 << evc_tpb(K, sizeof(R) == 8)) void k_evc_pass(
     constexpr int TS = 1 << K;
     constexpr int Q = K - 1 - TPB;
     constexpr int NQ = 1 << Q;
+    static_assert(K <= kEvcWiShift && Q + 1 <= 32 - kEvcWiShift, "EvcTerm::ztw fields overlap");
     __shared__ V lds[TS];
     __shared__ double red[NT / 64];
     const uint64_t base = spread(blockIdx.x, a.tphys, K);
+    const uint32_t blk = blockIdx.x;
     stage_tile<V, K, TPB, int8_t>(lds, psi + base, a.tphys);
     __syncthreads();
     double acc = 0.0;
     const char *lb = (const char *)lds;
+    // A pass's groups hold consecutive term ranges, so each group's first
+    // term follows from the previous group's count.
+    int tcur = a.ngroups > 0 ? groups[a.group0].t0 : 0;
     for (int gi = 0; gi < a.ngroups; ++gi) {
         const EvcGroup &G = groups[a.group0 + gi];
-        // every descriptor field first (scalar loads share the LDS counter:
-        // a scalar load between LDS reads would drain them)
+        // every descriptor field and the group's first four terms first
+        // (scalar loads share the LDS counter: a scalar load between LDS
+        // reads would drain them)
         const uint32_t xl = G.xl;
         const int hb = G.hbit;
         const int need = G.need;
-        const int t0 = G.t0, t1 = G.t0 + G.nt;
+        const int nt = G.nt;
         int wb[Q > 0 ? Q : 1];
 #pragma unroll
         for (int b = 0; b < Q; ++b) wb[b] = G.wbits[b];
+        EvcTerm T0[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) T0[u] = terms[tcur + u];
+        // pin the term loads here, so that one wait covers them and the
+        // descriptor (left alone, the compiler sinks them to their use)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) asm volatile("" ::"s"(T0[u].coef), "s"(T0[u].ztw), "s"(T0[u].zb));
+        asm volatile("" ::"s"(nt));
         // The thread-index bits are the lowest TPB tile bits other than the
         // half-space bit hb (the group layout the planner builds), so the
         // thread's tile index is threadIdx.x with a zero inserted at hb.
@@ -937,28 +951,33 @@ __global__ __launch_bounds__(1 << evc_tpb(K, sizeof(R) == 8)) void k_evc_pass(
         }
         if (need & 1) wht<R, NQ>(re);
         if (need & 2) wht<R, NQ>(im);
-        // terms four at a time: all descriptor loads first, then one wait
-        int ti = t0;
+        // tt < 2^kEvcWiShift, so the Walsh index in the high bits of ztw
+        // drops out of tt & ztw.
+        auto term = [&](const EvcTerm &T) {
+            const uint32_t wi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(T.ztw >> kEvcWiShift));
+            const uint32_t par = __builtin_popcount(tt & T.ztw) + __builtin_popcount(blk & T.zb);
+            acc += T.coef * (double)neg_if_odd(w[wi], par);
+        };
+        if (nt >= 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) term(T0[u]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+                if (u < nt) term(T0[u]);
+        }
+        // the rest four at a time (one 64-byte scalar load), then one wait
+        const int t1 = tcur + nt;
+        int ti = tcur + 4;
         for (; ti + 4 <= t1; ti += 4) {
             EvcTerm T[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) T[u] = terms[ti + u];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t wi = (uint32_t)__builtin_amdgcn_readfirstlane(
-                    (int)((T[u].zw & (NQ - 1)) | (T[u].use_im ? NQ : 0)));
-                const uint32_t par =
-                    __builtin_popcount(tt & T[u].zt) + __builtin_popcountll(base & T[u].zg);
-                acc += T[u].coef * (double)neg_if_odd(w[wi], par);
-            }
+            for (int u = 0; u < 4; ++u) term(T[u]);
         }
-        for (; ti < t1; ++ti) {
-            const EvcTerm &T = terms[ti];
-            const uint32_t wi = (uint32_t)__builtin_amdgcn_readfirstlane(
-                (int)((T.zw & (NQ - 1)) | (T.use_im ? NQ : 0)));
-            const uint32_t par = __builtin_popcount(tt & T.zt) + __builtin_popcountll(base & T.zg);
-            acc += T.coef * (double)neg_if_odd(w[wi], par);
-        }
+        for (; ti < t1; ++ti) term(terms[ti]);
+        tcur = t1;
     }
     const double s = block_sum(acc, red);
     if (threadIdx.x == 0) partials[a.part0 + blockIdx.x] = s;

@@ -1368,6 +1368,15 @@ static uint32_t pext32(uint32_t v, const int32_t *bits, int nb) {
     return out;
 }
 
+// The bits of v at the positions set in m, packed towards bit 0.
+static uint64_t pext64(uint64_t v, uint64_t m) {
+    uint64_t out = 0;
+    int i = 0;
+    for (; m; m &= m - 1, ++i)
+        if (v & m & (~m + 1)) out |= 1ULL << i;
+    return out;
+}
+
 std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched sched, int k,
                         int c, bool dbl, const std::vector<int> &pos0, PauliPlan &out) {
     out = PauliPlan();
@@ -1596,6 +1605,9 @@ std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched 
                 for (uint64_t s = S; s; s &= s - 1) tph[j++] = (int8_t)__builtin_ctzll(s);
             }
             std::memcpy(ea.tphys, tph, 16);
+            // the block index's bits are the physical bits outside the tile,
+            // in ascending order
+            const uint64_t nontile = ~S & ((n >= 64 ? 0 : (1ULL << n)) - 1);
             ea.group0 = (int)out.groups.size();
             ea.ngroups = (int)pg.size();
             ea.nblocks = 1 << (n - keff);
@@ -1650,25 +1662,26 @@ std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched 
                     const int nY = popc(terms[t].x & terms[t].z);
                     EvcTerm et;
                     std::memset(&et, 0, sizeof(et));
+                    int use_im;
                     if (xl) {
                         // pair (j, j^x) over j with bit h clear:
                         // nY even: 2 (-1)^{nY/2} s_j Re w ; nY odd: 2 (-1)^{(nY+1)/2} s_j Im w
                         if ((nY & 1) == 0) {
                             et.coef = 2.0 * terms[t].coef * (((nY / 2) & 1) ? -1.0 : 1.0);
-                            et.use_im = 0;
+                            use_im = 0;
                         } else {
                             et.coef = 2.0 * terms[t].coef * ((((nY + 1) / 2) & 1) ? -1.0 : 1.0);
-                            et.use_im = 1;
+                            use_im = 1;
                         }
                     } else {
                         et.coef = terms[t].coef;
-                        et.use_im = (zl >> G.hbit) & 1;   // difference array
+                        use_im = (zl >> G.hbit) & 1;   // difference array
                     }
                     const uint32_t zr = zl & ~(1u << G.hbit);
-                    et.zg = zg;
-                    et.zt = zr & tmask;
-                    et.zw = pext32(zr, G.wbits, Q);
-                    G.need |= et.use_im ? 2 : 1;
+                    const uint32_t wi = pext32(zr, G.wbits, Q) | (use_im ? 1u << Q : 0u);
+                    et.ztw = (zr & tmask) | (wi << kEvcWiShift);
+                    et.zb = (uint32_t)pext64(zg, nontile);
+                    G.need |= use_im ? 2 : 1;
                     out.terms.push_back(et);
                     HpsiTerm ht;
                     std::memset(&ht, 0, sizeof(ht));
@@ -1701,6 +1714,10 @@ std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched 
         if (!rem.empty()) return "internal: Pauli packing left groups uncovered";
         ++qrtile;
     }
+    // The Pauli pass loads a group's first four terms with its descriptor,
+    // before it knows the group's term count: four zero terms at the end
+    // keep those loads inside the table.
+    out.terms.resize(out.terms.size() + 4, EvcTerm{});
     return "";
 }
 

@@ -117,27 +117,35 @@ struct PassArgs {
 };
 
 // Read-only Pauli pass (EVC) and H|psi> pass.
+// The fields the Pauli pass reads per group come first (one 32-byte scalar
+// load); the stride is a power of two.
 struct EvcGroup {
     uint32_t xl;          // tile-local flip mask (0 for the diagonal group)
     int32_t hbit;         // tile-local half-space bit (the pair partner flips it)
-    int32_t t0, nt;       // term range
-    int32_t tbits[16];    // tile-local bits of the thread index (low to high)
-    int32_t wbits[8];     // tile-local bits of the per-thread cube index
+    int32_t nt;           // term count
     int32_t need;         // bit0: real array used, bit1: imaginary array used
-    int32_t pad;
+    int32_t wbits[4];     // tile-local bits of the per-thread cube index (Q <= 3)
+    int32_t t0;           // first term
+    int32_t pad[7];
+    int32_t tbits[16];    // tile-local bits of the thread index (low to high)
 };
+static_assert(sizeof(EvcGroup) == 128, "EvcGroup layout");
+
+// Bits kEvcWiShift and up of EvcTerm::ztw hold the term's index into the
+// per-thread Walsh arrays: the z bits in cube-index coordinates, plus the
+// cube size when the term reads the imaginary (or difference) array.
+constexpr int kEvcWiShift = 24;
 
 struct EvcTerm {
     double coef;          // a_t with the i^{nY} sign and pair factor folded in
-    uint64_t zg;          // physical z bits outside the tile (per-tile sign)
-    uint32_t zt;          // tile-local z bits on thread-index bits
-    uint32_t zw;          // z bits in cube-index coordinates (Walsh index)
-    int32_t use_im;       // 1: imaginary (or difference) array
-    int32_t pad;
+    uint32_t ztw;         // bits 0..23: tile-local z bits on thread-index bits;
+                          // bits 24..28: Walsh-array index (see above)
+    uint32_t zb;          // z bits outside the tile in block-index coordinates
+                          // (tile sign = parity of blockIdx & zb)
 };
 
-// The EVC pass reads a term as two 16-byte words per lane.
-static_assert(sizeof(EvcTerm) == 32, "EvcTerm layout");
+// Four terms are one 64-byte scalar load.
+static_assert(sizeof(EvcTerm) == 16, "EvcTerm layout");
 
 struct EvcPassArgs {
     int32_t ngroups;
