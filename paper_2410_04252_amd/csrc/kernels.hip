@@ -987,6 +987,66 @@ __global__ __launch_bounds__(1 << evc_tpb(K, sizeof(R) == 8)) void k_evc_pass(
 // H|psi> pass
 // ---------------------------------------------------------------------------
 
+// One H|psi> group's terms, accumulated into the per-thread spectra fr/fi
+// (index: the term's cube z bits; sign: the parity of the thread's and the
+// tile's z bits).  T0 holds the group's first four terms, loaded with its
+// descriptor; the rest are read four at a time.  sthr < 2^kHpsiZwShift, so
+// the cube bits in the high part of ztw drop out of sthr & ztw.
+template <typename R, int NQ>
+__device__ __forceinline__ void hpsi_terms(const HpsiTerm *__restrict__ terms, const HpsiTerm *T0,
+                                           int t0, int nt, uint32_t sthr, uint32_t tile, R *fr, R *fi) {
+    auto term = [&](const HpsiTerm &T) {
+        const uint32_t zw =
+            (uint32_t)__builtin_amdgcn_readfirstlane((int)(T.ztw >> kHpsiZwShift)) & (NQ - 1);
+        const uint32_t par = __builtin_popcount(sthr & T.ztw) + __builtin_popcount(tile & T.zb);
+        R ar, ai;
+        if constexpr (sizeof(R) == 4) {
+            ar = T.are_f;
+            ai = T.aim_f;
+        } else {
+            ar = T.are;
+            ai = T.aim;
+        }
+        fr[zw] += neg_if_odd(ar, par);
+        fi[zw] += neg_if_odd(ai, par);
+    };
+    if (nt >= 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) term(T0[u]);
+    } else {
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+            if (u < nt) term(T0[u]);
+    }
+    const int t1 = t0 + nt;
+    int ti = t0 + 4;
+    for (; ti + 4 <= t1; ti += 4) {
+        HpsiTerm T[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) T[u] = terms[ti + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) term(T[u]);
+    }
+    for (; ti < t1; ++ti) term(terms[ti]);
+}
+
+// The first four terms of a group (the term table ends in four zero terms,
+// so these loads stay inside it), pinned next to the descriptor loads so
+// that one wait covers both.
+template <typename R>
+__device__ __forceinline__ void hpsi_first_terms(const HpsiTerm *__restrict__ terms, int t0,
+                                                 HpsiTerm *T0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) T0[u] = terms[t0 + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if constexpr (sizeof(R) == 4)
+            asm volatile("" ::"s"(T0[u].are_f), "s"(T0[u].aim_f), "s"(T0[u].ztw), "s"(T0[u].zb));
+        else
+            asm volatile("" ::"s"(T0[u].are), "s"(T0[u].aim), "s"(T0[u].ztw), "s"(T0[u].zb));
+    }
+}
+
 template <typename R, int K>
 __global__ __launch_bounds__(1 << hpsi_tpb(K)) void k_hpsi_pass(
     const typename V2T<R>::type *__restrict__ psi, typename V2T<R>::type *__restrict__ lam,
@@ -1005,31 +1065,40 @@ __global__ __launch_bounds__(1 << hpsi_tpb(K)) void k_hpsi_pass(
 #pragma unroll
     for (int jj = 0; jj < NQ; ++jj) lr[jj] = li[jj] = 0.0;
     const uint32_t tid = threadIdx.x;
+    // a pass's groups hold consecutive term ranges
+    int tcur = a.ngroups > 0 ? groups[a.group0].t0 : 0;
     for (int gi = 0; gi < a.ngroups; ++gi) {
         const HpsiGroup &G = groups[a.group0 + gi];
-        const uint32_t sthr = tid ^ G.xt;
+        const uint32_t xt = G.xt;
+        const int nt = G.nt;
+        HpsiTerm T0[4];
+        hpsi_first_terms<R>(terms, tcur, T0);
+        asm volatile("" ::"s"(xt), "s"(nt));
+        const uint32_t sthr = tid ^ xt;
         R fr[NQ], fi[NQ];
 #pragma unroll
         for (int jj = 0; jj < NQ; ++jj) fr[jj] = fi[jj] = (R)0;
-        const int t1 = G.t0 + G.nt;
-        for (int ti = G.t0; ti < t1; ++ti) {
-            const HpsiTerm &T = terms[ti];
-            const uint32_t zw = (uint32_t)__builtin_amdgcn_readfirstlane((int)T.zw) & (NQ - 1);
-            const uint32_t par = (__builtin_popcount(sthr & T.zt) + __builtin_popcountll(base & T.zg)) & 1u;
-            const R ar = (R)T.are, ai = (R)T.aim;
-            fr[zw] += par ? -ar : ar;
-            fi[zw] += par ? -ai : ai;
-        }
+        hpsi_terms<R, NQ>(terms, T0, tcur, nt, sthr, blockIdx.x, fr, fi);
+        tcur += nt;
         wht<R, NQ>(fr);
         wht<R, NQ>(fi);
+        // The planner folded (-1)^(zw . xw) into each term's coefficient, so
+        // the transform's output jj is the spectrum at the source's cube
+        // index jj ^ xw (an XOR shift): the spectra are indexed at compile
+        // time and only the LDS address depends on xw.  Reads in batches of
+        // eight, all issued before their products.
         const uint32_t xw = (uint32_t)__builtin_amdgcn_readfirstlane((int)G.xw);
 #pragma unroll
-        for (int jj = 0; jj < NQ; ++jj) {
-            const uint32_t sc = (jj ^ xw) & (NQ - 1);
-            const R f_r = fr[sc], f_i = fi[sc];
-            const V p = lds[sthr | (sc << TPB)];
-            lr[jj] += (double)(f_r * p.x - f_i * p.y);
-            li[jj] += (double)(f_r * p.y + f_i * p.x);
+        for (int j0 = 0; j0 < NQ; j0 += 8) {
+            V p[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) p[u] = lds[sthr | ((((uint32_t)(j0 + u)) ^ xw) & (NQ - 1)) << TPB];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int jj = j0 + u;
+                lr[jj] += (double)(fr[jj] * p[u].x - fi[jj] * p[u].y);
+                li[jj] += (double)(fr[jj] * p[u].y + fi[jj] * p[u].x);
+            }
         }
     }
     uint32_t tpo = 0;
@@ -1680,31 +1749,39 @@ __device__ __forceinline__ void hpsi_item(const BatchArgs &a, const BatchInst &N
 #pragma unroll
     for (int jj = 0; jj < HNQ; ++jj) lr[jj] = li[jj] = 0.0;
     const uint32_t tid = threadIdx.x;
+    int tcur = hp.ngroups > 0 ? a.hgroups[hp.group0].t0 : 0;
     for (int gi = 0; gi < hp.ngroups; ++gi) {
         const HpsiGroup &G = a.hgroups[hp.group0 + gi];
-        const uint32_t sthr = tid ^ G.xt;
+        const uint32_t xt = G.xt;
+        const int nt = G.nt;
+        HpsiTerm T0[4];
+        hpsi_first_terms<R>(a.hterms, tcur, T0);
+        asm volatile("" ::"s"(xt), "s"(nt));
+        const uint32_t sthr = tid ^ xt;
         R fr[HNQ], fi[HNQ];
 #pragma unroll
         for (int jj = 0; jj < HNQ; ++jj) fr[jj] = fi[jj] = (R)0;
-        const int t1 = G.t0 + G.nt;
-        for (int ti = G.t0; ti < t1; ++ti) {
-            const HpsiTerm &T = a.hterms[ti];
-            const uint32_t zw = (uint32_t)__builtin_amdgcn_readfirstlane((int)T.zw) & (HNQ - 1);
-            const uint32_t par = (__builtin_popcount(sthr & T.zt) + __builtin_popcountll(base & T.zg)) & 1u;
-            const R ar = (R)T.are, ai = (R)T.aim;
-            fr[zw] += par ? -ar : ar;
-            fi[zw] += par ? -ai : ai;
-        }
+        hpsi_terms<R, HNQ>(a.hterms, T0, tcur, nt, sthr, tile, fr, fi);
+        tcur += nt;
         wht<R, HNQ>(fr);
         wht<R, HNQ>(fi);
+        // The planner folded (-1)^(zw . xw) into each term's coefficient, so
+        // the transform's output jj is the spectrum at the source's cube
+        // index jj ^ xw (an XOR shift): the spectra are indexed at compile
+        // time and only the LDS address depends on xw.  Reads in batches of
+        // eight, all issued before their products.
         const uint32_t xw = (uint32_t)__builtin_amdgcn_readfirstlane((int)G.xw);
 #pragma unroll
-        for (int jj = 0; jj < HNQ; ++jj) {
-            const uint32_t sc = (jj ^ xw) & (HNQ - 1);
-            const R f_r = fr[sc], f_i = fi[sc];
-            const V p = lds[sthr | (sc << HTPB)];
-            lr[jj] += (double)(f_r * p.x - f_i * p.y);
-            li[jj] += (double)(f_r * p.y + f_i * p.x);
+        for (int j0 = 0; j0 < HNQ; j0 += 8) {
+            V p[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) p[u] = lds[sthr | ((((uint32_t)(j0 + u)) ^ xw) & (HNQ - 1)) << HTPB];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int jj = j0 + u;
+                lr[jj] += (double)(fr[jj] * p[u].x - fi[jj] * p[u].y);
+                li[jj] += (double)(fr[jj] * p[u].y + fi[jj] * p[u].x);
+            }
         }
     }
     uint32_t tpo = 0;

@@ -1692,9 +1692,16 @@ std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched 
                     case 2: ht.are = -a; ht.aim = 0; break;
                     default: ht.are = 0; ht.aim = -a; break;
                     }
-                    ht.zg = zg;
-                    ht.zt = zl & htmask;
-                    ht.zw = zl >> TPBH;
+                    // (-1)^(cube z bits . xw): the H|psi> pass reads the
+                    // transformed spectrum XOR-shifted by xw
+                    if (__builtin_popcount((zl >> TPBH) & HG.xw) & 1) {
+                        ht.are = -ht.are;
+                        ht.aim = -ht.aim;
+                    }
+                    ht.are_f = (float)ht.are;
+                    ht.aim_f = (float)ht.aim;
+                    ht.ztw = (zl & htmask) | ((zl >> TPBH) << kHpsiZwShift);
+                    ht.zb = (uint32_t)pext64(zg, nontile);
                     out.hterms.push_back(ht);
                 }
                 out.groups.push_back(G);
@@ -1714,10 +1721,11 @@ std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched 
         if (!rem.empty()) return "internal: Pauli packing left groups uncovered";
         ++qrtile;
     }
-    // The Pauli pass loads a group's first four terms with its descriptor,
+    // The Pauli and H|psi> passes load a group's first four terms with its descriptor,
     // before it knows the group's term count: four zero terms at the end
     // keep those loads inside the table.
     out.terms.resize(out.terms.size() + 4, EvcTerm{});
+    out.hterms.resize(out.hterms.size() + 4, HpsiTerm{});
     return "";
 }
 

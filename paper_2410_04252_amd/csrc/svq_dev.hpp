@@ -164,12 +164,18 @@ struct HpsiGroup {
     int32_t pad;
 };
 
+// Bits kHpsiZwShift and up of HpsiTerm::ztw hold the term's z bits in cube
+// coordinates (its index into the per-thread spectra).
+constexpr int kHpsiZwShift = 24;
+
 struct HpsiTerm {
+    float are_f, aim_f;   // a_t * i^{nY}, rounded to single precision
+    uint32_t ztw;         // bits 0..23: z bits on thread-index bits; bits 24..: cube z bits
+    uint32_t zb;          // z bits outside the tile in tile-index coordinates
+                          // (tile sign = parity of tile index & zb)
     double are, aim;      // a_t * i^{nY}
-    uint64_t zg;
-    uint32_t zt;
-    uint32_t zw;
 };
+static_assert(sizeof(HpsiTerm) == 32, "HpsiTerm layout");
 
 struct HpsiPassArgs {
     int32_t ngroups;
