@@ -1086,15 +1086,16 @@ __global__ __launch_bounds__(1 << hpsi_tpb(K)) void k_hpsi_pass(
         // the transform's output jj is the spectrum at the source's cube
         // index jj ^ xw (an XOR shift): the spectra are indexed at compile
         // time and only the LDS address depends on xw.  Reads in batches of
-        // eight, all issued before their products.
+        // up to eight, all issued before their products.
         const uint32_t xw = (uint32_t)__builtin_amdgcn_readfirstlane((int)G.xw);
+        constexpr int PB = NQ < 8 ? NQ : 8;   // reads per batch
 #pragma unroll
-        for (int j0 = 0; j0 < NQ; j0 += 8) {
-            V p[8];
+        for (int j0 = 0; j0 < NQ; j0 += PB) {
+            V p[PB];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) p[u] = lds[sthr | ((((uint32_t)(j0 + u)) ^ xw) & (NQ - 1)) << TPB];
+            for (int u = 0; u < PB; ++u) p[u] = lds[sthr | ((((uint32_t)(j0 + u)) ^ xw) & (NQ - 1)) << TPB];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < PB; ++u) {
                 const int jj = j0 + u;
                 lr[jj] += (double)(fr[jj] * p[u].x - fi[jj] * p[u].y);
                 li[jj] += (double)(fr[jj] * p[u].y + fi[jj] * p[u].x);
@@ -1769,15 +1770,16 @@ __device__ __forceinline__ void hpsi_item(const BatchArgs &a, const BatchInst &N
         // the transform's output jj is the spectrum at the source's cube
         // index jj ^ xw (an XOR shift): the spectra are indexed at compile
         // time and only the LDS address depends on xw.  Reads in batches of
-        // eight, all issued before their products.
+        // up to eight, all issued before their products.
         const uint32_t xw = (uint32_t)__builtin_amdgcn_readfirstlane((int)G.xw);
+        constexpr int PB = HNQ < 8 ? HNQ : 8;   // reads per batch
 #pragma unroll
-        for (int j0 = 0; j0 < HNQ; j0 += 8) {
-            V p[8];
+        for (int j0 = 0; j0 < HNQ; j0 += PB) {
+            V p[PB];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) p[u] = lds[sthr | ((((uint32_t)(j0 + u)) ^ xw) & (HNQ - 1)) << HTPB];
+            for (int u = 0; u < PB; ++u) p[u] = lds[sthr | ((((uint32_t)(j0 + u)) ^ xw) & (HNQ - 1)) << HTPB];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < PB; ++u) {
                 const int jj = j0 + u;
                 lr[jj] += (double)(fr[jj] * p[u].x - fi[jj] * p[u].y);
                 li[jj] += (double)(fr[jj] * p[u].y + fi[jj] * p[u].x);
