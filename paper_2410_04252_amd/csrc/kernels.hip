@@ -537,7 +537,7 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
     constexpr int NT = 1 << (K - RB);
     constexpr int NW = NT / 64;
     constexpr int NWB = K - RB - 6;
-    __shared__ V lds[(ADJ ? 2 : 1) << K];
+    __shared__ V lds[1 << K];
     __shared__ double gacc[ADJ ? kGradCap * NW : 1];
     if (blockIdx.x >= ntiles) return;
     // Workgroups are dealt to the 8 XCDs round robin (block b runs on XCD
@@ -582,38 +582,33 @@ __global__ __launch_bounds__(1 << (K - RB)) void k_gate_pass(
     for (int s = 0; s < np; ++s) {
         const PhaseDesc &Pc = phases[a.phase0 + (ADJ ? np - 1 - s : s)];
         if (s > 0) {
-            // transpose through LDS: write with the old mapping, read with the new
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                const uint32_t ad = sw ^ mc.slot(j);
-                V e;
-                e.x = v.re[j];
-                e.y = v.im[j];
-                lds[ad] = e;
-                if constexpr (ADJ) {
-                    V f;
-                    f.x = w.re[j];
-                    f.y = w.im[j];
-                    lds[(1 << K) + ad] = f;
-                }
-            }
-            __syncthreads();
+            // transpose through LDS: write with the old mapping, read with the
+            // new.  The reverse pass moves psi and then lam through the same
+            // tile buffer (half the LDS of two buffers: more blocks per CU).
+            const uint32_t swo = sw;
+            const RegMap<RB, K> mo = mc;
             uint32_t tpx;
             thread_maps<NWB, K>(Pc, a.tphys, lane, wave, tpx, sw);
             mc.init(Pc, a.tphys);
+            auto transpose = [&](Regs<R, NR> &r) {
+                __syncthreads();
 #pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                const uint32_t ad = sw ^ mc.slot(j);
-                const V e = lds[ad];
-                v.re[j] = e.x;
-                v.im[j] = e.y;
-                if constexpr (ADJ) {
-                    const V f = lds[(1 << K) + ad];
-                    w.re[j] = f.x;
-                    w.im[j] = f.y;
+                for (int j = 0; j < NR; ++j) {
+                    V e;
+                    e.x = r.re[j];
+                    e.y = r.im[j];
+                    lds[swo ^ mo.slot(j)] = e;
                 }
-            }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    const V e = lds[sw ^ mc.slot(j)];
+                    r.re[j] = e.x;
+                    r.im[j] = e.y;
+                }
+            };
+            transpose(v);
+            if constexpr (ADJ) transpose(w);
         }
         const int nop = Pc.nop;
         const int op0 = Pc.op0;
@@ -1667,30 +1662,27 @@ __device__ __forceinline__ void gate_item(const BatchArgs &a, const BatchInst &N
     for (int s = 0; s < np; ++s) {
         const PhaseDesc &Pc = a.phases[bp.phase0 + (ADJ ? np - 1 - s : s)];
         if (s > 0) {
-            if constexpr (NW == 1) __builtin_amdgcn_wave_barrier();
-            else __syncthreads();
-#pragma unroll
-            for (int j = 0; j < NRT; ++j) {
-                const uint32_t ad = sw ^ mc.slot(j);
-                lds[ad] = make_float2(v.re[j], v.im[j]);
-                if constexpr (ADJ) lds[(1 << KT) + ad] = make_float2(w.re[j], w.im[j]);
-            }
-            __syncthreads();
+            // psi, then lam (reverse items), through the one tile buffer
+            const uint32_t swo = sw;
+            const RegMap<RBT, KT> mo = mc;
             uint32_t tpx;
             thread_maps<NWB, KT>(Pc, bp.tphys, lane, wave, tpx, sw);
             mc.init(Pc, bp.tphys);
+            auto transpose = [&](Regs<R, NRT> &r, bool after_read) {
+                if (NW == 1 && !after_read) __builtin_amdgcn_wave_barrier();
+                else __syncthreads();
 #pragma unroll
-            for (int j = 0; j < NRT; ++j) {
-                const uint32_t ad = sw ^ mc.slot(j);
-                const V e = lds[ad];
-                v.re[j] = e.x;
-                v.im[j] = e.y;
-                if constexpr (ADJ) {
-                    const V f = lds[(1 << KT) + ad];
-                    w.re[j] = f.x;
-                    w.im[j] = f.y;
+                for (int j = 0; j < NRT; ++j) lds[swo ^ mo.slot(j)] = make_float2(r.re[j], r.im[j]);
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < NRT; ++j) {
+                    const V e = lds[sw ^ mc.slot(j)];
+                    r.re[j] = e.x;
+                    r.im[j] = e.y;
                 }
-            }
+            };
+            transpose(v, false);
+            if constexpr (ADJ) transpose(w, true);
             if constexpr (NW == 1) __syncthreads();
         }
         const int nop = Pc.nop;
@@ -1874,7 +1866,7 @@ __device__ __forceinline__ void stamp_done(const BatchArgs &a, int inst) {
 // bounded by spin_limit sleeps, after which the error flag is set and all
 // blocks drain.
 __global__ __launch_bounds__(64) void k_batch(const BatchArgs a) {
-    __shared__ float2 lds[2 << kBatchK];
+    __shared__ float2 lds[1 << kBatchK];
     const uint32_t lane = threadIdx.x & 63u;
     if (blockIdx.x == 0 && lane == 0) *a.t_start = __builtin_amdgcn_s_memrealtime();
     for (;;) {
@@ -1940,10 +1932,8 @@ __global__ __launch_bounds__(64) void k_batch(const BatchArgs a) {
 template <int TYPE>
 __global__ __launch_bounds__((TYPE == IT_FWD_W || TYPE == IT_ADJ_W || TYPE == IT_HPSI_W) ? 256 : 64) void
 k_batch_stage(const BatchArgs a, int item0) {
-    constexpr int NLDS = TYPE == IT_ADJ_W ? (2 << kBatchKWide)
-                       : (TYPE == IT_FWD_W || TYPE == IT_HPSI_W) ? (1 << kBatchKWide)
-                       : TYPE == IT_ADJ ? (2 << kBatchK)
-                       : (TYPE == IT_FWD || TYPE == IT_HPSI) ? (1 << kBatchK) : 1;
+    constexpr int NLDS = (TYPE == IT_ADJ_W || TYPE == IT_FWD_W || TYPE == IT_HPSI_W) ? (1 << kBatchKWide)
+                       : (TYPE == IT_ADJ || TYPE == IT_FWD || TYPE == IT_HPSI) ? (1 << kBatchK) : 1;
     constexpr int NGW = TYPE == IT_ADJ_W ? kGradCap * 4 : 1;
     __shared__ float2 lds[NLDS];
     __shared__ double gacc[NGW];
