@@ -1721,9 +1721,18 @@ std::string plan_paulis(int n, int g, const svq_pauli *terms, int nt, svq_sched 
         if (!rem.empty()) return "internal: Pauli packing left groups uncovered";
         ++qrtile;
     }
-    // The Pauli and H|psi> passes load a group's first four terms with its descriptor,
-    // before it knows the group's term count: four zero terms at the end
-    // keep those loads inside the table.
+    // The Pauli and H|psi> passes find a group's first term from the previous
+    // group's range and load its first four terms with its descriptor,
+    // before they know its term count: the ranges of a pass must be
+    // consecutive, and four zero terms at the end keep those loads inside
+    // the table.  (groups and hgroups are filled in step: one index.)
+    for (const EvcPassArgs &ea : out.passes)
+        for (int i = 1; i < ea.ngroups; ++i) {
+            const EvcGroup &p = out.groups[ea.group0 + i - 1], &q = out.groups[ea.group0 + i];
+            const HpsiGroup &hp = out.hgroups[ea.group0 + i - 1], &hq = out.hgroups[ea.group0 + i];
+            if (q.t0 != p.t0 + p.nt || hq.t0 != hp.t0 + hp.nt)
+                return "internal: a Pauli pass's term ranges are not consecutive";
+        }
     out.terms.resize(out.terms.size() + 4, EvcTerm{});
     out.hterms.resize(out.hterms.size() + 4, HpsiTerm{});
     return "";
