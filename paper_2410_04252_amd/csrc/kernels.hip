@@ -1928,9 +1928,13 @@ __global__ __launch_bounds__(64) void k_batch(const BatchArgs a) {
 // items of that level, block b running item item0 + b to the end.  Stream
 // order between the launches carries every dependency, so no block waits,
 // and each item type gets a kernel of its own (registers and LDS sized for
-// that type alone rather than for the largest of all types).
+// that type alone rather than for the largest of all types).  The 2^12
+// reverse and H|psi> items are held to four blocks per CU (128 VGPRs, no
+// spills; their LDS allows four and five): left alone they take 163 and
+// 149 VGPRs, three blocks.  The forward item would spill at 128.
 template <int TYPE>
-__global__ __launch_bounds__((TYPE == IT_FWD_W || TYPE == IT_ADJ_W || TYPE == IT_HPSI_W) ? 256 : 64) void
+__global__ __launch_bounds__((TYPE == IT_FWD_W || TYPE == IT_ADJ_W || TYPE == IT_HPSI_W) ? 256 : 64,
+                             (TYPE == IT_ADJ_W || TYPE == IT_HPSI_W) ? 4 : 1) void
 k_batch_stage(const BatchArgs a, int item0) {
     constexpr int NLDS = (TYPE == IT_ADJ_W || TYPE == IT_FWD_W || TYPE == IT_HPSI_W) ? (1 << kBatchKWide)
                        : (TYPE == IT_ADJ || TYPE == IT_FWD || TYPE == IT_HPSI) ? (1 << kBatchK) : 1;
