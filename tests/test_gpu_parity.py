@@ -321,6 +321,31 @@ def test_dense_matrix_gates_forward_and_gradient(P, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("k", [8, 9, 10, 11, 12, 13])
+def test_apply_hamiltonian_every_tile_width(P, dtype, k, monkeypatch):
+    """lambda = H psi with the H|psi> tile forced to 2^k amplitudes, against
+    the oracle: k = 8 gives each thread a 4-entry spectrum, k = 9 an 8-entry
+    one, k >= 10 a 16-entry one, so every batch width of the pass's output
+    reads and every spectrum size of the XOR-shifted term signs runs."""
+    n, g = 14, 1
+    ham = W.jw_terms(n, 150, 505 + k)
+    v = W.random_state(n, 506 + k, np.complex64 if dtype == "c64" else np.complex128)
+    ref = oracle.hpsi(v.astype(np.complex128), ham)
+    monkeypatch.setenv("SVQ_EVC_K", str(k))
+    st = P.State(n, g, dtype)
+    out = P.State(n, g, dtype)
+    st.set_amplitudes(v)
+    st.qr_permute([int(x) for x in np.random.default_rng(507 + k).permutation(n)])
+    out.qr_permute(st.layout())
+    _print(f"apply_hamiltonian tile k={k} {dtype}")
+    P.sv_apply_hamiltonian(st.h, P.paulis_array(ham), len(ham.coef), out.h)
+    got = out.get_amplitudes()
+    assert np.max(np.abs(got - ref)) <= AMP[dtype] * max(1.0, float(np.abs(ham.coef).sum()))
+    st.close()
+    out.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("case", ["jw15", "random9-wide"])
 def test_apply_hamiltonian_parity(P, dtype, case):
     """lambda = H psi through sv_apply_hamiltonian (the adjoint seed) on a
