@@ -321,6 +321,28 @@ def test_dense_matrix_gates_forward_and_gradient(P, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("k", [8, 9, 10, 11, 12, 13, 14])
+def test_expectation_every_tile_width(P, dtype, k, monkeypatch):
+    """E through the Pauli pass with its tile forced to 2^k amplitudes (2^13
+    at most for complex128), against the oracle: k = 8 and 9 give 2- and
+    4-pair cubes, k >= 10 8-pair cubes; groups with one to many strings
+    exercise the first-four-terms load and the four-at-a-time loop."""
+    n, g = 15, 1
+    ham = W.jw_terms(n, 300, 508 + k)
+    v = W.random_state(n, 509 + k, np.complex64 if dtype == "c64" else np.complex128)
+    monkeypatch.setenv("SVQ_EVC_K", str(k))
+    st = P.State(n, g, dtype)
+    st.set_amplitudes(v)
+    st.qr_permute([int(x) for x in np.random.default_rng(510 + k).permutation(n)])
+    _print(f"expectation tile k={k} {dtype}")
+    e, stats = st.expectation(ham)
+    assert stats.tile_k == (min(k, 13) if dtype == "c128" else k)
+    ok, rel = energy_ok(e, oracle.expectation(v.astype(np.complex128), ham), None, ham, dtype)
+    assert ok, rel
+    st.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("k", [8, 9, 10, 11, 12, 13])
 def test_apply_hamiltonian_every_tile_width(P, dtype, k, monkeypatch):
     """lambda = H psi with the H|psi> tile forced to 2^k amplitudes, against
