@@ -660,6 +660,34 @@ __device__ __forceinline__ uint64_t apply_pairs(uint64_t x, const int8_t *pairs,
 // a wave swaps row r with row pi(r) (once, from the smaller side) with fully
 // coalesced loads and stores.  Each wave owns U consecutive rows, so that 2U
 // loads are in flight before the first store; one launch covers every row.
+// A reorder pass streams 16-byte amplitudes with non-temporal accesses (as
+// the complex128 gate pass does) and 8-byte ones with plain accesses.
+template <typename V>
+__device__ __forceinline__ V ld_amp(const V *p) {
+    if constexpr (sizeof(V) == 16) {
+        typedef double d2_t __attribute__((ext_vector_type(2)));
+        const d2_t t = __builtin_nontemporal_load((const d2_t *)p);
+        V v;
+        v.x = t.x;
+        v.y = t.y;
+        return v;
+    } else {
+        return *p;
+    }
+}
+template <typename V>
+__device__ __forceinline__ void st_amp(V *p, const V &v) {
+    if constexpr (sizeof(V) == 16) {
+        typedef double d2_t __attribute__((ext_vector_type(2)));
+        d2_t t;
+        t.x = v.x;
+        t.y = v.y;
+        __builtin_nontemporal_store(t, (d2_t *)p);
+    } else {
+        *p = v;
+    }
+}
+
 template <typename V, int U>
 __global__ __launch_bounds__(256) void k_qr_rows(V *__restrict__ psi, const QrArgs a) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -701,15 +729,15 @@ __global__ __launch_bounds__(256) void k_qr_rows(V *__restrict__ psi, const QrAr
         ra[u] = ((uint64_t)r << 6) | lane;
         rb[u] = ((uint64_t)pr << 6) | lane;
         if (act[u]) {
-            x[u] = psi[ra[u]];
-            y[u] = psi[rb[u]];
+            x[u] = ld_amp(psi + ra[u]);
+            y[u] = ld_amp(psi + rb[u]);
         }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         if (act[u]) {
-            psi[ra[u]] = y[u];
-            psi[rb[u]] = x[u];
+            st_amp(psi + ra[u], y[u]);
+            st_amp(psi + rb[u], x[u]);
         }
     }
 }
@@ -760,8 +788,8 @@ __global__ __launch_bounds__(256) void k_qr_tiles(V *__restrict__ psi, const QrA
     V x[E], y[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        x[e] = psi[b + off[e]];
-        if (pb != b) y[e] = psi[pb + off[e]];
+        x[e] = ld_amp(psi + b + off[e]);
+        if (pb != b) y[e] = ld_amp(psi + pb + off[e]);
     }
     // LDS slot of tile element i: the element bits above one bank row
     // (256 bytes) are folded into the bits below it.  An in-tile transposition
@@ -780,8 +808,8 @@ __global__ __launch_bounds__(256) void k_qr_tiles(V *__restrict__ psi, const QrA
     for (int e = 0; e < E; ++e) {
         const uint32_t t = threadIdx.x + 256u * e;
         const uint32_t q = slot(t);
-        psi[pb + off[e]] = l0[q];
-        if (pb != b) psi[b + off[e]] = l1[q];
+        st_amp(psi + pb + off[e], l0[q]);
+        if (pb != b) st_amp(psi + b + off[e], l1[q]);
     }
 }
 
