@@ -660,8 +660,9 @@ __device__ __forceinline__ uint64_t apply_pairs(uint64_t x, const int8_t *pairs,
 // a wave swaps row r with row pi(r) (once, from the smaller side) with fully
 // coalesced loads and stores.  Each wave owns U consecutive rows, so that 2U
 // loads are in flight before the first store; one launch covers every row.
-// A reorder pass streams 16-byte amplitudes with non-temporal accesses (as
-// the complex128 gate pass does) and 8-byte ones with plain accesses.
+// 16-byte amplitudes stream with non-temporal accesses (reorder passes and
+// tile staging, as in the complex128 gate pass); 8-byte ones use plain
+// accesses (their non-temporal stores are several times slower).
 template <typename V>
 __device__ __forceinline__ V ld_amp(const V *p) {
     if constexpr (sizeof(V) == 16) {
@@ -847,7 +848,8 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 
 // Stage one tile into LDS: every thread issues all of its loads before the
 // first LDS write.  Thread bits are the tile's low bits (coalesced); the
-// offsets of the high part are uniform.
+// offsets of the high part are uniform.  16-byte amplitudes are read with
+// non-temporal loads.
 template <typename V, int K, int TPB, typename TI>
 __device__ __forceinline__ void stage_tile(V *lds, const V *__restrict__ src, const TI *tphys) {
     constexpr int NT = 1 << TPB;
@@ -863,7 +865,7 @@ __device__ __forceinline__ void stage_tile(V *lds, const V *__restrict__ src, co
 #pragma unroll
         for (int b = 0; b < K - TPB; ++b)
             if ((e >> b) & 1) hp |= 1u << tphys[TPB + b];
-        x[e] = src[tp + hp];
+        x[e] = ld_amp(src + tp + hp);
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) lds[tid + NT * e] = x[e];
